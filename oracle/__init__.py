@@ -1,0 +1,356 @@
+"""Python handle on the FP64 CPU oracle (oracle/msgpm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product path.  Argument marshalling
+only; every step of the method runs in the C oracle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "msgpm_oracle.c")
+LIB = os.path.join(_HERE, "libmsgpm_oracle.so")
+
+PI_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "support", "count", "hyp",
+             "hyp_count", "refit", "detected", "rk", "pass", "valid"]
+PI = {n: i for i, n in enumerate(PI_FIELDS)}
+
+F_COST, F_ROUND, F_COLOUR, F_FB, F_BOUNDS, F_RANSAC = 1, 2, 4, 8, 16, 32
+B_RCOUNT, B_SYMCOUNT = 64, 128
+
+DEFAULTS = dict(C=5, r=4, grad_weight=1.0, blocks=(64, 32, 16), iters=8, hyps=256, R0=0, tau=1.0, eps=0.1,
+                tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False)
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", LIB, SRC,
+           "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER(_Pair)
+        vp = ctypes.c_void_p
+        i = ctypes.c_int
+        sig = {
+            "orc_philox4x64": (None, [vp, vp, vp]),
+            "orc_draw": (ctypes.c_uint32, [ctypes.c_uint64, ctypes.c_uint32]),
+            "orc_features": (None, [vp, i, i, i, i, vp]),
+            "orc_round_fp16": (ctypes.c_float, [ctypes.c_float]),
+            "orc_project": (i, [vp, ctypes.c_double, ctypes.c_double, vp, vp]),
+            "orc_cost": (ctypes.c_double, [P, i, i, i, i, i, vp]),
+            "orc_cost_all": (None, [P, i, vp]),
+            "orc_block_count": (i, [i, i]),
+            "orc_block_origin": (i, [i, i, i]),
+            "orc_plane_capacity": (i, [P]),
+            "orc_plane_index": (i, [P, i, i, i, i]),
+            "orc_m_min": (i, [P, i, i]),
+            "orc_planes_init": (None, [P]),
+            "orc_nnf_init": (None, [P, i]),
+            "orc_eval_cost": (None, [P, i, i]),
+            "orc_pm_halfsweep": (None, [P, i, i, i, i, i]),
+            "orc_ransac": (None, [P, i, i, i]),
+            "orc_dlt4": (i, [vp, vp, vp, vp, vp]),
+            "orc_refit": (i, [vp, vp, vp, vp, i, vp]),
+            "orc_gauss_solve": (i, [vp, vp, i, vp]),
+            "orc_colour_err": (ctypes.c_double, [P, i, i, i, vp, vp]),
+            "orc_assign": (None, [P, i, i, i, i]),
+            "orc_symmetry": (None, [P, i, i]),
+            "orc_fb_test": (i, [P, i, i, i, vp, vp, vp]),
+            "orc_fb_unassign": (None, [P]),
+            "orc_nnf_update": (None, [P, i, i]),
+            "orc_finalize": (None, [P, i, vp, vp]),
+            "orc_solve": (None, [P, vp, vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class _Pair(ctypes.Structure):
+    _fields_ = [
+        ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("C", ctypes.c_int32), ("r", ctypes.c_int32),
+        ("wc", ctypes.c_double * 5),
+        ("F", ctypes.c_void_p * 2),
+        ("n_levels", ctypes.c_int32), ("block", ctypes.c_int32 * 8),
+        ("iters", ctypes.c_int32), ("hyps", ctypes.c_int32), ("R0", ctypes.c_int32), ("m_min_abs", ctypes.c_int32),
+        ("eta_num", ctypes.c_int32), ("eta_den", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("eps", ctypes.c_double), ("tau_fb", ctypes.c_double), ("mu", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("nnf", ctypes.c_void_p * 2), ("cost", ctypes.c_void_p * 2), ("win", ctypes.c_void_p * 2),
+        ("loss", ctypes.c_void_p * 2), ("hlabel", ctypes.c_void_p * 2), ("twin", ctypes.c_void_p * 2),
+        ("tloss", ctypes.c_void_p * 2), ("pflag", ctypes.c_void_p * 2),
+        ("P", ctypes.c_int32), ("pH", ctypes.c_void_p), ("pinfo", ctypes.c_void_p), ("bflag", ctypes.c_void_p),
+        ("evals", ctypes.c_int64),
+    ]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x64(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def draw(word: int, n: int) -> int:
+    return int(lib().orc_draw(ctypes.c_uint64(word), n))
+
+
+def features(rgb: np.ndarray, C: int = 5, fp16: bool = False) -> np.ndarray:
+    rgb = np.ascontiguousarray(rgb, dtype=np.float32)
+    H, W, _ = rgb.shape
+    out = np.zeros((H, W, C), dtype=np.float32)
+    lib().orc_features(_ptr(rgb), W, H, C, int(fp16), _ptr(out))
+    return out
+
+
+def round_fp16(x: float) -> float:
+    return float(lib().orc_round_fp16(x))
+
+
+def dlt4(src, dst):
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    dst = np.ascontiguousarray(dst, dtype=np.float64)
+    Hm = np.zeros(9)
+    ok = lib().orc_dlt4(_ptr(np.ascontiguousarray(src[:, 0])), _ptr(np.ascontiguousarray(src[:, 1])),
+                        _ptr(np.ascontiguousarray(dst[:, 0])), _ptr(np.ascontiguousarray(dst[:, 1])), _ptr(Hm))
+    return Hm.reshape(3, 3) if ok else None
+
+
+def refit(src, dst):
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    dst = np.ascontiguousarray(dst, dtype=np.float64)
+    cols = [np.ascontiguousarray(a) for a in (src[:, 0], src[:, 1], dst[:, 0], dst[:, 1])]
+    Hm = np.zeros(9)
+    ok = lib().orc_refit(*[_ptr(c) for c in cols], len(src), _ptr(Hm))
+    return Hm.reshape(3, 3) if ok else None
+
+
+def gauss_solve(A, b):
+    A = np.ascontiguousarray(A, dtype=np.float64).copy()
+    b = np.ascontiguousarray(b, dtype=np.float64).copy()
+    x = np.zeros(len(b))
+    ok = lib().orc_gauss_solve(_ptr(A), _ptr(b), len(b), _ptr(x))
+    return x if ok else None
+
+
+def pack(dx, dy) -> np.ndarray:
+    dx = np.asarray(dx, dtype=np.int64)
+    dy = np.asarray(dy, dtype=np.int64)
+    return ((dx & 0xFFFF) | ((dy & 0xFFFF) << 16)).astype(np.uint32).view(np.int32)
+
+
+def unpack(v):
+    v = np.asarray(v).astype(np.int32).view(np.uint32)
+    dx = (v & 0xFFFF).astype(np.uint16).view(np.int16).astype(np.int32)
+    dy = (v >> 16).astype(np.uint16).view(np.int16).astype(np.int32)
+    return dx, dy
+
+
+class Oracle:
+    """One frame pair with its full per-direction state, driven phase by phase
+    or end to end.  Arrays are numpy and may be read or overwritten between
+    phases (to feed identical state to another implementation)."""
+
+    def __init__(self, frame1: np.ndarray, frame2: np.ndarray, **params):
+        p = dict(DEFAULTS)
+        p.update(params)
+        self.params = p
+        self.Hh, self.Ww = frame1.shape[:2]
+        H, W = self.Hh, self.Ww
+        C = p["C"]
+        self.feat = [features(frame1, C, p["fp16"]), features(frame2, C, p["fp16"])]
+        n = W * H
+        self.nnf = [np.zeros(n, np.int32) for _ in range(2)]
+        self.cost = [np.zeros(n, np.float64) for _ in range(2)]
+        self.win = [np.full(n, -1, np.int32) for _ in range(2)]
+        self.loss = [np.full(n, np.inf) for _ in range(2)]
+        self.hlabel = [np.full(n, -1, np.int32) for _ in range(2)]
+        self.twin = [np.full(n, -1, np.int32) for _ in range(2)]
+        self.tloss = [np.full(n, np.inf) for _ in range(2)]
+        self.pflag = [np.zeros(n, np.uint8) for _ in range(2)]
+        s = _Pair()
+        s.W, s.H, s.C, s.r = W, H, C, p["r"]
+        g = p["grad_weight"]
+        for i, v in enumerate([1.0, 1.0, 1.0, g, g]):
+            s.wc[i] = v
+        blocks = list(p["blocks"])
+        s.n_levels = len(blocks)
+        for i, b in enumerate(blocks):
+            s.block[i] = b
+        s.iters, s.hyps, s.R0, s.m_min_abs = p["iters"], p["hyps"], p["R0"], p["m_min_abs"]
+        s.eta_num, s.eta_den = p["eta"]
+        s.tau, s.eps, s.tau_fb, s.mu = p["tau"], p["eps"], p["tau_fb"], p["mu"]
+        s.seed = p["seed"]
+        self.s = s
+        self._bind()
+        P = lib().orc_plane_capacity(ctypes.byref(s))
+        s.P = P
+        self.pH = np.zeros((P, 9), np.float64)
+        self.pinfo = np.zeros((P, len(PI_FIELDS)), np.int32)
+        self.bflag = np.zeros(P, np.uint8)
+        s.pH, s.pinfo, s.bflag = _ptr(self.pH), _ptr(self.pinfo), _ptr(self.bflag)
+        lib().orc_planes_init(ctypes.byref(s))
+
+    def _bind(self):
+        s = self.s
+        s.F[0], s.F[1] = _ptr(self.feat[0]), _ptr(self.feat[1])
+        for d in range(2):
+            s.nnf[d] = _ptr(self.nnf[d])
+            s.cost[d] = _ptr(self.cost[d])
+            s.win[d] = _ptr(self.win[d])
+            s.loss[d] = _ptr(self.loss[d])
+            s.hlabel[d] = _ptr(self.hlabel[d])
+            s.twin[d] = _ptr(self.twin[d])
+            s.tloss[d] = _ptr(self.tloss[d])
+            s.pflag[d] = _ptr(self.pflag[d])
+
+    @property
+    def ref(self):
+        self._bind()
+        return ctypes.byref(self.s)
+
+    @property
+    def evals(self) -> int:
+        return int(self.s.evals)
+
+    # -- helpers ---------------------------------------------------------
+    def plane_index(self, d, level, stage, block):
+        return lib().orc_plane_index(self.ref, d, level, stage, block)
+
+    def block_grid(self, level):
+        B = self.params["blocks"][level]
+        return lib().orc_block_count(self.Ww, B), lib().orc_block_count(self.Hh, B)
+
+    def m_min(self, bw, bh):
+        return lib().orc_m_min(self.ref, bw, bh)
+
+    def cost_at(self, d, px, py, tx, ty, Hm=None):
+        h = None if Hm is None else _ptr(np.ascontiguousarray(Hm, dtype=np.float64).reshape(9))
+        return lib().orc_cost(self.ref, d, px, py, tx, ty, h)
+
+    def cost_all(self, d):
+        n = self.Ww * self.Hh
+        out = np.zeros(n * n)
+        lib().orc_cost_all(self.ref, d, _ptr(out))
+        return out.reshape(n, n)
+
+    def colour_err(self, d, px, py, Hm):
+        h = np.ascontiguousarray(Hm, dtype=np.float64).reshape(9)
+        nb = ctypes.c_int(0)
+        return lib().orc_colour_err(self.ref, d, px, py, _ptr(h), ctypes.byref(nb))
+
+    # -- phases ----------------------------------------------------------
+    def nnf_init(self, d):
+        lib().orc_nnf_init(self.ref, d)
+
+    def set_nnf(self, d, nnf):
+        """Install a caller-supplied NNF, clamping targets into the frame."""
+        W, H = self.Ww, self.Hh
+        dx, dy = unpack(np.asarray(nnf).reshape(-1))
+        x = np.arange(W * H) % W
+        y = np.arange(W * H) // W
+        tx = np.clip(x + dx, 0, W - 1)
+        ty = np.clip(y + dy, 0, H - 1)
+        self.nnf[d][:] = pack(tx - x, ty - y)
+
+    def eval_cost(self, d, mode):
+        lib().orc_eval_cost(self.ref, d, mode)
+
+    def pm_halfsweep(self, d, colour, it, slot, restricted):
+        lib().orc_pm_halfsweep(self.ref, d, colour, it, slot, restricted)
+
+    def pm_pass(self, slot, restricted):
+        for it in range(self.params["iters"]):
+            for colour in range(2):
+                for d in range(2):
+                    self.pm_halfsweep(d, colour, it, slot, restricted)
+
+    def ransac(self, d, level, stage):
+        lib().orc_ransac(self.ref, d, level, stage)
+
+    def assign(self, d, level, stage, tentative):
+        lib().orc_assign(self.ref, d, level, stage, int(tentative))
+
+    def symmetry(self, level, stage):
+        lib().orc_symmetry(self.ref, level, stage)
+
+    def fb_unassign(self):
+        lib().orc_fb_unassign(self.ref)
+
+    def nnf_update(self, d, level):
+        lib().orc_nnf_update(self.ref, d, level)
+
+    def finalize(self, d):
+        W, H = self.Ww, self.Hh
+        flow = np.zeros((H, W, 2), np.float32)
+        occ = np.zeros((H, W), np.uint8)
+        lib().orc_finalize(self.ref, d, _ptr(flow), _ptr(occ))
+        return flow, occ
+
+    def reset_state(self):
+        for d in range(2):
+            self.win[d][:] = -1
+            self.loss[d][:] = np.inf
+            self.hlabel[d][:] = -1
+            self.pflag[d][:] = 0
+        lib().orc_planes_init(self.ref)
+
+    def solve(self, init_nnf=(None, None)):
+        W, H = self.Ww, self.Hh
+        flows = [np.zeros((H, W, 2), np.float32) for _ in range(2)]
+        occs = [np.zeros((H, W), np.uint8) for _ in range(2)]
+        inits = []
+        for a in init_nnf:
+            inits.append(None if a is None else np.ascontiguousarray(a, dtype=np.int32).reshape(-1))
+        lib().orc_solve(self.ref, None if inits[0] is None else _ptr(inits[0]),
+                        None if inits[1] is None else _ptr(inits[1]), _ptr(flows[0]), _ptr(flows[1]),
+                        _ptr(occs[0]), _ptr(occs[1]))
+        return flows, occs
+
+    def run_level_schedule(self):
+        """Yields (name, args) of every phase of the pipeline in order, for
+        lock-step comparisons; the caller runs each phase."""
+        p = self.params
+        yield ("eval_cost", (0, 0))
+        yield ("eval_cost", (1, 0))
+        for it in range(p["iters"]):
+            for colour in range(2):
+                yield ("pm_halfsweep", (colour, it, 0, 0))
+        for lv in range(len(p["blocks"])):
+            for stage in (1, 2):
+                yield ("ransac", (lv, stage))
+                yield ("assign", (lv, stage, 1))
+                yield ("symmetry", (lv, stage))
+                yield ("assign", (lv, stage, 0))
+            yield ("fb_unassign", ())
+            yield ("nnf_update", (lv,))
+            yield ("eval_cost", (0, 1))
+            yield ("eval_cost", (1, 1))
+            for it in range(p["iters"]):
+                for colour in range(2):
+                    yield ("pm_halfsweep", (colour, it, lv + 1, 1))
