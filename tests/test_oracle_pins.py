@@ -761,3 +761,35 @@ def test_end_to_end_sanity_tiny(tiny_pair):
     assert epe[vis & assigned].mean() < 0.5
     assert occs[0][tiny_pair.occ == 1].mean() > 0.8
     assert assigned[vis].mean() > 0.8
+
+
+def test_luma_weights_per_channel():
+    for ch, wgt in [(0, 0.299), (1, 0.587), (2, 0.114)]:
+        img = np.zeros((5, 6, 3), np.float32)
+        img[..., ch] = np.arange(6, dtype=np.float32)[None, :] * 0.5
+        f = oracle.features(img, C=5)
+        assert np.allclose(f[:, 2, 3], wgt * 0.5, rtol=1e-6), ch
+        assert np.allclose(f[:, 2, 4], 0.0)
+
+
+def test_ransac_ties_keep_lowest_hypothesis():
+    """On an exact plane every accepted hypothesis has the full count, so the
+    winner is the first hypothesis that is not rejected; the draw of
+    hypothesis h does not depend on K, so that index is found by growing K."""
+    W = H = 16
+
+    def fn(xs, ys):
+        return xs + 3, ys - 2
+
+    first = None
+    for K in range(1, 40):
+        o = _ransac_oracle(W, H, 16, fn, hyps=K, seed=5)
+        o.ransac(0, 0, 1)
+        k = o.plane_index(0, 0, 1, 0)
+        if o.pinfo[k, PI["hyp"]] >= 0:
+            first = K - 1
+            break
+    assert first is not None
+    o = _ransac_oracle(W, H, 16, fn, hyps=256, seed=5)
+    o.ransac(0, 0, 1)
+    assert o.pinfo[o.plane_index(0, 0, 1, 0), PI["hyp"]] == first
