@@ -1,0 +1,203 @@
+/*
+ * msgpm.h - C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of multi-scale generalized plane match (MSGPM): Choi & Banerjee,
+ * "Multi-Scale Generalized Plane Match for Optical Flow", arXiv 1804.03787.
+ *
+ * Problem statement (Sec. 3, Alg. 1): two frames in, optional initial nearest-
+ * neighbour field (NNF), patch size, list of plane-fit window sizes (one per
+ * level) and iteration counts; dense flow, per-window homographies and an
+ * occlusion mask out, for both directions (frame 1 -> 2 and frame 2 -> 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are device pointers (HIP global memory of the current
+ *    device); everything else is host memory.  The caller owns every buffer,
+ *    including the workspace; the library allocates no device memory.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and the
+ *    call returns once it is enqueued.  Calls on one workspace must be ordered
+ *    on one stream.
+ *  - Pixel (x, y) has index y*width + x; y points down; pixel centres are on
+ *    integer coordinates.  A flow or NNF offset is target - source.
+ *  - NNF offsets are packed int32: (dx & 0xffff) | (dy << 16), both int16.
+ *  - Direction 0 matches frame 1 against frame 2, direction 1 frame 2 against
+ *    frame 1; every phase entry point processes both directions.
+ *  - Homographies are row-major 3x3 doubles mapping a source-frame pixel to the
+ *    target frame (Eq. 1), normalised so that H[8] = 1.
+ *  - Errors are returned as msgpm_status; nothing is thrown across the ABI.
+ *    msgpm_last_error() returns a message for the calling thread's last error.
+ *    On an error nothing is enqueued.
+ */
+#ifndef MSGPM_H
+#define MSGPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSGPM_MAX_LEVELS 8
+
+typedef enum msgpm_status {
+  MSGPM_OK = 0,
+  MSGPM_E_INVALID = 1,     /* bad argument: sizes, parameters, null pointer */
+  MSGPM_E_DEVICE = 3,      /* the HIP runtime reported an error */
+  MSGPM_E_UNSUPPORTED = 4  /* valid but not built (e.g. patch radius > 4) */
+} msgpm_status;
+
+/* Storage flag: features stored as binary16 (FP16) with FP32 accumulation. */
+#define MSGPM_FLAG_FP16 1u
+
+/* Method parameters.  Defaults in brackets are those of the 1024x436 workload. */
+typedef struct msgpm_params {
+  int32_t width, height;     /* frame size, 2..32767 each */
+  int32_t channels;          /* 3 = RGB, 5 = RGB + luma gradients gx, gy [5] */
+  int32_t patch_radius;      /* r: square patch of (2r+1)^2 taps, 1..4 [4] (Sec. 4 uses 7x7) */
+  int32_t n_levels;          /* number of plane-fit levels, 0..8 [3] (Sec. 3.3) */
+  int32_t block[MSGPM_MAX_LEVELS]; /* window side per level, largest first, 4..128 [64, 32, 16];
+                                      windows overlap by half (Sec. 3.1.2) */
+  int32_t pm_iters;          /* PatchMatch iterations per pass [8] */
+  int32_t ransac_hyps;       /* RANSAC hypotheses per window, 1..1024 [256] (Sec. 3.1.2) */
+  int32_t search_radius0;    /* first random-search radius; 0 = max(width, height) */
+  int32_t min_support_abs;   /* detection needs max(this, ceil(frac * window area)) inliers [8] */
+  int32_t eta_num, eta_den;  /* plane-symmetry ratio eta = num/den [1/2] (Alg. 1, Sec. 3.4) */
+  uint32_t flags;            /* MSGPM_FLAG_* */
+  double grad_weight;        /* weight of gx, gy in the patch cost [1] */
+  double inlier_px;          /* RANSAC reprojection threshold tau in pixels [1] */
+  double eps_color;          /* colour-consistency threshold epsilon, RMS over RGB [0.1] (Eq. 4) */
+  double fb_px;              /* forward-backward point threshold in pixels [1] */
+  double min_support_frac;   /* see min_support_abs [0.25] */
+  uint64_t seed;             /* key of the counter-based random stream */
+} msgpm_params;
+
+/* Per-window plane record, 144 bytes.  One record per (direction, level,
+   stage, window); the record index is
+     dir * n_planes/2 + 2 * (windows of the levels before) + (stage-1) * windows(level) + window
+   with windows numbered row-major over their origins. */
+typedef struct msgpm_plane {
+  double H[9];               /* fitted homography (source -> target), H[8] = 1 when fitted */
+  int32_t dir, level, stage, block;
+  int32_t x0, y0, bw, bh;    /* window rectangle */
+  int32_t support;           /* points handed to RANSAC (stage 2: the window's unassigned pixels) */
+  int32_t count;             /* inliers of H */
+  int32_t hyp, hyp_count;    /* winning hypothesis and its inliers (-1, 0 if none) */
+  int32_t refit;             /* 1 if the least-squares refit replaced the hypothesis */
+  int32_t detected;          /* count >= minimum support */
+  int32_t rk, pass;          /* colour-consistent pixels and those passing forward-backward */
+  int32_t valid;             /* detected and kept by the plane-symmetry test */
+  int32_t reserved;
+} msgpm_plane;
+
+/* Byte offsets of every array inside the caller-allocated workspace (one per
+   frame pair), each 256-byte aligned.  Per-pixel arrays hold width*height
+   elements; [d] indexes the direction. */
+typedef struct msgpm_layout {
+  uint64_t total_bytes;
+  uint64_t feat[2];        /* features of frame 1 and frame 2, see below */
+  uint64_t feat_bytes;     /* bytes of one frame's features */
+  uint64_t nnf[2];         /* int32 packed offsets */
+  uint64_t cost[2];        /* float: warped-patch SSD of the current offset */
+  uint64_t win[2];         /* int32: assigned plane index, -1 = unassigned */
+  uint64_t loss[2];        /* double: colour-consistency loss of the assignment */
+  uint64_t hlabel[2];      /* int32: region plane used for the patch distortion, -1 = identity */
+  uint64_t twin[2];        /* int32: tentative assignment (scratch) */
+  uint64_t tloss[2];       /* double: its loss (scratch) */
+  uint64_t planes;         /* msgpm_plane[n_planes] */
+  uint64_t counters;       /* uint64[8]: [0], [1] warped-patch evaluations per direction */
+  int32_t n_planes;
+  int32_t n_levels;
+  int32_t level_blocks[MSGPM_MAX_LEVELS]; /* windows per level and stage */
+  int32_t level_nbx[MSGPM_MAX_LEVELS];    /* windows per row */
+} msgpm_layout;
+/* Feature storage of one frame (FP32): width*height float4 (R, G, B, gx or 0)
+   followed, when channels = 5, by width*height float (gy).  FP16: width*height
+   records of 8 halves (R, G, B, gx, gy, 0, 0, 0). */
+
+/* Fills *out for the given parameters; validates them.  No device work. */
+msgpm_status msgpm_layout_query(const msgpm_params* p, msgpm_layout* out);
+
+/* Text of the calling thread's last error ("" if none).  Owned by the library. */
+const char* msgpm_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Whole pipeline (Alg. 1 for every level, Sec. 3.4 forward-backward check at
+ * the end of each level, Sec. 4 set-up): features, initial NNF (random unless
+ * given), PatchMatch init pass, then per level two plane stages (Sec. 3.1,
+ * 3.2), FB, NNF update (Sec. 3.3.1) and a PatchMatch pass restricted to the
+ * unassigned pixels (Sec. 3.3.2).
+ *   d_rgb1, d_rgb2: frames, height x width x 3 float32 (HWC).
+ *   d_init_nnf0/1:  optional initial NNF per direction (packed, may be NULL).
+ *   d_ws:           workspace of layout.total_bytes, 256-byte aligned.
+ *   d_flow0/1:      height x width x 2 float32: plane flow where a plane is
+ *                   assigned, else the NNF offset.
+ *   d_occ0/1:       height x width uint8: 1 = no plane assigned (occluded,
+ *                   Sec. 3.4).
+ * The plane table stays in the workspace (layout.planes).
+ * ------------------------------------------------------------------------- */
+msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                         const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws,
+                         float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Phase entry points.  Each runs one step of the pipeline on the state held in
+ * the workspace, for both directions, exactly as msgpm_solve does; together
+ * they let a caller run, inspect or replace the state between steps.
+ * ------------------------------------------------------------------------- */
+
+/* Features of both frames (pixel colours plus optional luma gradients gx, gy
+   with replicate borders; the paper's cost is colour only, Sec. 3.1.3). */
+msgpm_status msgpm_features(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2, void* d_ws,
+                            void* stream);
+
+/* Initial state: NNF from d_init_nnf0/1 (targets clamped into the frame) or, if
+   NULL, a uniformly random target per pixel from the counter-based stream;
+   every pixel unassigned with the identity region plane; plane table reset;
+   evaluation counters zeroed. */
+msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
+                              void* d_ws, void* stream);
+
+/* Recomputes the warped-patch cost of the current offset.  mode 0: every pixel
+   under the identity; mode 1: unassigned pixels under their region plane;
+   mode 2: assigned pixels under their assigned plane. */
+msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* stream);
+
+/* One red-black half-sweep of PatchMatch (propagation from the four
+   neighbours, then random search; Barnes et al. as used in Sec. 3.1) over the
+   pixels with (x + y) % 2 == colour.  restricted = 0: every pixel, identity
+   patch; restricted = 1: unassigned pixels only, patches distorted by the region
+   plane, plus the candidate that plane predicts (Sec. 3.3.2).  iter and slot
+   (0 = initial pass, level + 1 = pass after that level) key the random stream. */
+msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, int iter, int slot, int restricted,
+                                void* stream);
+
+/* RANSAC plane fit in every window of `level` (Sec. 3.1.2; stage 2 = residual
+   region, Sec. 3.2): writes the (level, stage) plane records. */
+msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stage, void* stream);
+
+/* Colour-consistency assignment (Eq. 3-4, overlap rule of Sec. 3.1.3 and the
+   level priority of Sec. 3.3).  tentative = 1 uses the detected planes and
+   writes twin/tloss; tentative = 0 uses the valid planes and updates win/loss. */
+msgpm_status msgpm_assign(const msgpm_params* p, void* d_ws, int level, int stage, int tentative, void* stream);
+
+/* Plane-symmetry test (Alg. 1, Sec. 3.4 first cue) of every detected plane of
+   (level, stage) against the other direction's tentative assignment. */
+msgpm_status msgpm_symmetry(const msgpm_params* p, void* d_ws, int level, int stage, void* stream);
+
+/* End-of-level forward-backward check (Sec. 4): assigned pixels failing it
+   become unassigned, both directions judged on the same snapshot. */
+msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream);
+
+/* NNF update from the assigned planes (Sec. 3.3.1) and region plane choice for
+   the next restricted pass. */
+msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void* stream);
+
+/* Outputs: refreshes the cost of assigned pixels, writes flow and occlusion
+   mask of both directions (see msgpm_solve). */
+msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
+                            uint8_t* d_occ1, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSGPM_H */

@@ -332,12 +332,11 @@ class Oracle:
                         _ptr(occs[0]), _ptr(occs[1]))
         return flows, occs
 
-    def run_level_schedule(self):
-        """Yields (name, args) of every phase of the pipeline in order, for
-        lock-step comparisons; the caller runs each phase."""
+    def schedule(self):
+        """Every phase of the pipeline after the initial state, in order, as
+        (name, args) pairs covering both directions; run_step executes one."""
         p = self.params
-        yield ("eval_cost", (0, 0))
-        yield ("eval_cost", (1, 0))
+        yield ("eval_cost", (0,))
         for it in range(p["iters"]):
             for colour in range(2):
                 yield ("pm_halfsweep", (colour, it, 0, 0))
@@ -349,8 +348,14 @@ class Oracle:
                 yield ("assign", (lv, stage, 0))
             yield ("fb_unassign", ())
             yield ("nnf_update", (lv,))
-            yield ("eval_cost", (0, 1))
-            yield ("eval_cost", (1, 1))
+            yield ("eval_cost", (1,))
             for it in range(p["iters"]):
                 for colour in range(2):
                     yield ("pm_halfsweep", (colour, it, lv + 1, 1))
+
+    def run_step(self, name, args):
+        if name in ("symmetry", "fb_unassign"):
+            getattr(self, name)(*args)
+            return
+        for d in range(2):
+            getattr(self, name)(d, *args)

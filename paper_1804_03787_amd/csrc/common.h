@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP translation units of libmsgpm.
+// Written for gfx950 (CDNA4): wave64, 256-thread workgroups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/msgpm.h"
+
+namespace msgpm {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Parameters as kernels see them (passed by value).
+struct DevParams {
+  int W, H, C, r;
+  int iters, hyps, R0, nk;   // nk: number of random-search radii
+  int m_min_abs, eta_num, eta_den, fp16;
+  int n_levels;
+  int block[MSGPM_MAX_LEVELS];
+  int nbx[MSGPM_MAX_LEVELS], nby[MSGPM_MAX_LEVELS];
+  int plane_off[MSGPM_MAX_LEVELS];  // 2 * windows of the levels before
+  int planes_per_dir;
+  float gw;                          // gradient-channel weight
+  double tau2, eps2, fb2, mu;
+  uint64_t seed;
+};
+
+// Typed views of the workspace.
+struct Ws {
+  const void* feat[2];  // float4 plane (+ float plane) or 8-half records
+  int32_t* nnf[2];
+  float* cost[2];
+  int32_t* win[2];
+  double* loss[2];
+  int32_t* hlabel[2];
+  int32_t* twin[2];
+  double* tloss[2];
+  msgpm_plane* planes;
+  unsigned long long* counters;
+};
+
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__host__ __device__ inline int32_t pack_off(int dx, int dy) {
+  return (int32_t)(((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16));
+}
+__host__ __device__ inline int off_dx(int32_t v) { return (int16_t)((uint32_t)v & 0xffffu); }
+__host__ __device__ inline int off_dy(int32_t v) { return (int16_t)((uint32_t)v >> 16); }
+
+// Workgroup index remapped so that each XCD (which receives every 8th
+// workgroup in dispatch order) works on one contiguous range of tiles, keeping
+// neighbouring tiles in the same L2.
+__device__ inline int xcd_remap(int bid, int nb) {
+  const int q = nb / kXcds, rem = nb % kXcds;
+  const int xcd = bid % kXcds, k = bid / kXcds;
+  const int base = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+  return base + k;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter c, key (k0, k1).
+__device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Integer in [0, n) from the top 32 bits of a word (multiply-shift).
+__device__ inline int draw_below(uint64_t w, uint32_t n) { return (int)(((w >> 32) * (uint64_t)n) >> 32); }
+
+__device__ inline uint64_t rng_word3(int phase, int dir, int slot, int stage) {
+  return ((uint64_t)phase << 24) | ((uint64_t)dir << 16) | ((uint64_t)slot << 8) | (uint64_t)stage;
+}
+
+// Plane record index (see msgpm_plane).
+__host__ __device__ inline int plane_index(const DevParams& P, int dir, int level, int stage, int block) {
+  return dir * P.planes_per_dir + P.plane_off[level] + (stage - 1) * P.nbx[level] * P.nby[level] + block;
+}
+
+// Window origin along an axis (windows overlap by half, the last is flush).
+__host__ __device__ inline int block_origin(int n, int B, int i) {
+  if (n <= B) return 0;
+  const int o = i * (B / 2);
+  return o > n - B ? n - B : o;
+}
+
+// Contiguous range [lo, hi] of windows covering coordinate c.
+__host__ __device__ inline void cover_range(int n, int B, int nb, int c, int& lo, int& hi) {
+  const int bw = B < n ? B : n;
+  const int S = B / 2;
+  if (n <= B) {
+    lo = hi = 0;
+    return;
+  }
+  lo = (c - bw < 0) ? 0 : ((c - bw) / S + 1);
+  if (lo > nb - 1) lo = nb - 1;
+  hi = (c >= n - bw) ? nb - 1 : (c / S);
+  if (hi > nb - 1) hi = nb - 1;
+}
+
+// ---- launch wrappers (defined in the .hip files) ---------------------------
+hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s);
+hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
+                             hipStream_t s);
+hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s);
+hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
+                               hipStream_t s);
+hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
+hipError_t launch_assign(const DevParams& P, const Ws& w, int level, int stage, int tentative, hipStream_t s);
+hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
+hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s);
+hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s);
+hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
+                           uint8_t* occ1, hipStream_t s);
+
+}  // namespace msgpm

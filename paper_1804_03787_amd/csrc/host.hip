@@ -1,0 +1,326 @@
+// Host side of the C ABI declared in include/msgpm.h: parameter validation,
+// workspace layout and the launch sequence of the pipeline.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "common.h"
+
+namespace msgpm {
+size_t ransac_smem_bytes(const DevParams& P, int level);
+}
+
+using namespace msgpm;
+
+namespace {
+
+thread_local std::string g_err;
+
+msgpm_status fail(msgpm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+msgpm_status fail(msgpm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+msgpm_status check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MSGPM_OK;
+  return fail(MSGPM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int block_count(int n, int B) {
+  if (n <= B) return 1;
+  const int S = B / 2;
+  int m = (n - B) / S + 1;
+  if ((n - B) % S) ++m;
+  return m;
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+// Validates *p and derives the kernel parameters and the workspace layout.
+msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
+  if (!p) return fail(MSGPM_E_INVALID, "params is NULL");
+  if (p->width < 2 || p->height < 2 || p->width > 32767 || p->height > 32767)
+    return fail(MSGPM_E_INVALID, "frame size %dx%d outside 2..32767", p->width, p->height);
+  if (p->channels != 3 && p->channels != 5) return fail(MSGPM_E_INVALID, "channels must be 3 or 5");
+  if (p->patch_radius < 1 || p->patch_radius > 4)
+    return fail(MSGPM_E_UNSUPPORTED, "patch_radius %d outside 1..4", p->patch_radius);
+  if (p->n_levels < 0 || p->n_levels > MSGPM_MAX_LEVELS) return fail(MSGPM_E_INVALID, "n_levels outside 0..8");
+  for (int l = 0; l < p->n_levels; ++l)
+    if (p->block[l] < 4 || p->block[l] > 128) return fail(MSGPM_E_INVALID, "block[%d] = %d outside 4..128", l, p->block[l]);
+  if (p->pm_iters < 0 || p->pm_iters > 1000) return fail(MSGPM_E_INVALID, "pm_iters outside 0..1000");
+  if (p->ransac_hyps < 1 || p->ransac_hyps > 1024) return fail(MSGPM_E_INVALID, "ransac_hyps outside 1..1024");
+  if (p->search_radius0 < 0 || p->search_radius0 > 32767) return fail(MSGPM_E_INVALID, "search_radius0 outside 0..32767");
+  if (p->min_support_abs < 0) return fail(MSGPM_E_INVALID, "min_support_abs < 0");
+  if (p->eta_den <= 0 || p->eta_num < 0) return fail(MSGPM_E_INVALID, "eta must be num >= 0, den > 0");
+  if (!(p->inlier_px > 0) || !(p->eps_color > 0) || !(p->fb_px > 0) || !(p->min_support_frac >= 0) ||
+      !(p->grad_weight >= 0))
+    return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
+  if (p->flags & ~MSGPM_FLAG_FP16) return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
+
+  DevParams d;
+  memset(&d, 0, sizeof d);
+  d.W = p->width;
+  d.H = p->height;
+  d.C = p->channels;
+  d.r = p->patch_radius;
+  d.iters = p->pm_iters;
+  d.hyps = p->ransac_hyps;
+  d.R0 = p->search_radius0 > 0 ? p->search_radius0 : (p->width > p->height ? p->width : p->height);
+  d.nk = 0;
+  while ((d.R0 >> d.nk) >= 1) ++d.nk;
+  d.m_min_abs = p->min_support_abs;
+  d.eta_num = p->eta_num;
+  d.eta_den = p->eta_den;
+  d.fp16 = (p->flags & MSGPM_FLAG_FP16) ? 1 : 0;
+  d.n_levels = p->n_levels;
+  int off = 0;
+  for (int l = 0; l < p->n_levels; ++l) {
+    d.block[l] = p->block[l];
+    d.nbx[l] = block_count(d.W, d.block[l]);
+    d.nby[l] = block_count(d.H, d.block[l]);
+    d.plane_off[l] = off;
+    off += 2 * d.nbx[l] * d.nby[l];
+  }
+  d.planes_per_dir = off;
+  d.gw = (float)p->grad_weight;
+  d.tau2 = p->inlier_px * p->inlier_px;
+  d.eps2 = p->eps_color * p->eps_color;
+  d.fb2 = p->fb_px * p->fb_px;
+  d.mu = p->min_support_frac;
+  d.seed = p->seed;
+  if (P) *P = d;
+
+  if (L) {
+    msgpm_layout o;
+    memset(&o, 0, sizeof o);
+    const uint64_t n = (uint64_t)d.W * d.H;
+    uint64_t cur = 0;
+    o.feat_bytes = d.fp16 ? n * 16 : n * 16 + (d.C == 5 ? n * 4 : 0);
+    for (int f = 0; f < 2; ++f) {
+      o.feat[f] = cur;
+      cur = align256(cur + o.feat_bytes);
+    }
+    for (int k = 0; k < 2; ++k) {
+      o.nnf[k] = cur;
+      cur = align256(cur + 4 * n);
+      o.cost[k] = cur;
+      cur = align256(cur + 4 * n);
+      o.win[k] = cur;
+      cur = align256(cur + 4 * n);
+      o.loss[k] = cur;
+      cur = align256(cur + 8 * n);
+      o.hlabel[k] = cur;
+      cur = align256(cur + 4 * n);
+      o.twin[k] = cur;
+      cur = align256(cur + 4 * n);
+      o.tloss[k] = cur;
+      cur = align256(cur + 8 * n);
+    }
+    o.planes = cur;
+    o.n_planes = 2 * d.planes_per_dir;
+    cur = align256(cur + (uint64_t)o.n_planes * sizeof(msgpm_plane));
+    o.counters = cur;
+    cur = align256(cur + 8 * sizeof(uint64_t));
+    o.total_bytes = cur;
+    o.n_levels = d.n_levels;
+    for (int l = 0; l < d.n_levels; ++l) {
+      o.level_blocks[l] = d.nbx[l] * d.nby[l];
+      o.level_nbx[l] = d.nbx[l];
+    }
+    *L = o;
+  }
+  return MSGPM_OK;
+}
+
+Ws make_ws(const msgpm_layout& L, void* base) {
+  char* b = static_cast<char*>(base);
+  Ws w;
+  for (int k = 0; k < 2; ++k) {
+    w.feat[k] = b + L.feat[k];
+    w.nnf[k] = reinterpret_cast<int32_t*>(b + L.nnf[k]);
+    w.cost[k] = reinterpret_cast<float*>(b + L.cost[k]);
+    w.win[k] = reinterpret_cast<int32_t*>(b + L.win[k]);
+    w.loss[k] = reinterpret_cast<double*>(b + L.loss[k]);
+    w.hlabel[k] = reinterpret_cast<int32_t*>(b + L.hlabel[k]);
+    w.twin[k] = reinterpret_cast<int32_t*>(b + L.twin[k]);
+    w.tloss[k] = reinterpret_cast<double*>(b + L.tloss[k]);
+  }
+  w.planes = reinterpret_cast<msgpm_plane*>(b + L.planes);
+  w.counters = reinterpret_cast<unsigned long long*>(b + L.counters);
+  return w;
+}
+
+struct Ctx {
+  DevParams P;
+  msgpm_layout L;
+  Ws w;
+  hipStream_t s;
+};
+
+msgpm_status open_ctx(const msgpm_params* p, void* ws, void* stream, Ctx* c) {
+  msgpm_status st = prepare(p, &c->P, &c->L);
+  if (st != MSGPM_OK) return st;
+  if (!ws) return fail(MSGPM_E_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MSGPM_E_INVALID, "workspace not 256-byte aligned");
+  c->w = make_ws(c->L, ws);
+  c->s = static_cast<hipStream_t>(stream);
+  return MSGPM_OK;
+}
+
+msgpm_status check_level(const Ctx& c, int level, int stage) {
+  if (level < 0 || level >= c.P.n_levels) return fail(MSGPM_E_INVALID, "level %d outside 0..%d", level, c.P.n_levels - 1);
+  if (stage != 1 && stage != 2) return fail(MSGPM_E_INVALID, "stage must be 1 or 2");
+  return MSGPM_OK;
+}
+
+msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
+  for (int it = 0; it < c.P.iters; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      msgpm_status st = check(launch_pm_halfsweep(c.P, c.w, colour, it, slot, restricted, c.s), "pm_halfsweep");
+      if (st != MSGPM_OK) return st;
+    }
+  return MSGPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* msgpm_last_error(void) { return g_err.c_str(); }
+
+msgpm_status msgpm_layout_query(const msgpm_params* p, msgpm_layout* out) {
+  if (!out) return fail(MSGPM_E_INVALID, "layout pointer is NULL");
+  return prepare(p, nullptr, out);
+}
+
+msgpm_status msgpm_features(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2, void* d_ws,
+                            void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
+  st = check(launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s), "features");
+  if (st != MSGPM_OK) return st;
+  return check(launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s), "features");
+}
+
+msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
+                              void* d_ws, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  return check(launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s), "init_state");
+}
+
+msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (mode < 0 || mode > 2) return fail(MSGPM_E_INVALID, "mode must be 0, 1 or 2");
+  return check(launch_eval_cost(c.P, c.w, mode, c.s), "eval_cost");
+}
+
+msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, int iter, int slot, int restricted,
+                                void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (colour != 0 && colour != 1) return fail(MSGPM_E_INVALID, "colour must be 0 or 1");
+  if (iter < 0 || slot < 0 || slot > 255) return fail(MSGPM_E_INVALID, "iter or slot out of range");
+  return check(launch_pm_halfsweep(c.P, c.w, colour, iter, slot, restricted ? 1 : 0, c.s), "pm_halfsweep");
+}
+
+msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
+  return check(launch_ransac(c.P, c.w, level, stage, c.s), "ransac");
+}
+
+msgpm_status msgpm_assign(const msgpm_params* p, void* d_ws, int level, int stage, int tentative, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
+  return check(launch_assign(c.P, c.w, level, stage, tentative ? 1 : 0, c.s), "assign");
+}
+
+msgpm_status msgpm_symmetry(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
+  return check(launch_symmetry(c.P, c.w, level, stage, c.s), "symmetry");
+}
+
+msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  return check(launch_fb_unassign(c.P, c.w, c.s), "fb_unassign");
+}
+
+msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if ((st = check_level(c, level, 1)) != MSGPM_OK) return st;
+  return check(launch_nnf_update(c.P, c.w, level, c.s), "nnf_update");
+}
+
+msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
+                            uint8_t* d_occ1, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  st = check(launch_eval_cost(c.P, c.w, 2, c.s), "eval_cost");
+  if (st != MSGPM_OK) return st;
+  return check(launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s), "finalize");
+}
+
+msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                         const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws, float* d_flow0,
+                         float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
+#define RUN(expr, what)                          \
+  do {                                           \
+    msgpm_status s_ = check((expr), what);       \
+    if (s_ != MSGPM_OK) return s_;               \
+  } while (0)
+  RUN(launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s), "features");
+  RUN(launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s), "features");
+  RUN(launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s), "init_state");
+  RUN(launch_eval_cost(c.P, c.w, 0, c.s), "eval_cost");
+  if ((st = run_pm_pass(c, 0, 0)) != MSGPM_OK) return st;
+  for (int l = 0; l < c.P.n_levels; ++l) {
+    for (int stage = 1; stage <= 2; ++stage) {
+      RUN(launch_ransac(c.P, c.w, l, stage, c.s), "ransac");
+      RUN(launch_assign(c.P, c.w, l, stage, 1, c.s), "assign");
+      RUN(launch_symmetry(c.P, c.w, l, stage, c.s), "symmetry");
+      RUN(launch_assign(c.P, c.w, l, stage, 0, c.s), "assign");
+    }
+    RUN(launch_fb_unassign(c.P, c.w, c.s), "fb_unassign");
+    RUN(launch_nnf_update(c.P, c.w, l, c.s), "nnf_update");
+    RUN(launch_eval_cost(c.P, c.w, 1, c.s), "eval_cost");
+    if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
+  }
+  RUN(launch_eval_cost(c.P, c.w, 2, c.s), "eval_cost");
+  RUN(launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s), "finalize");
+#undef RUN
+  return MSGPM_OK;
+}
+
+}  // extern "C"

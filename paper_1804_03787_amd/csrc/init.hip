@@ -1,0 +1,125 @@
+// Feature preparation and state initialisation.
+//
+// Features: the patch cost of the paper compares colours (Sec. 3.1.3); the cost
+// here may add luma gradients.  Luma Y = (0.299 R + 0.587 G) + 0.114 B in FP32
+// without contraction; gx = 0.5 (Y(x+1) - Y(x-1)), gy likewise, with replicate
+// borders.  Stored per pixel as float4 (R, G, B, gx) plus a float plane (gy), or
+// as 8 halves (R, G, B, gx, gy, 0, 0, 0) in the FP16 form.
+#include "common.h"
+
+#include <hip/hip_fp16.h>
+
+#pragma clang fp contract(off)
+
+namespace msgpm {
+
+__device__ inline float luma(const float* rgb, int p) {
+  const float t = 0.299f * rgb[3 * p];
+  const float u = 0.587f * rgb[3 * p + 1];
+  const float v = 0.114f * rgb[3 * p + 2];
+  return (t + u) + v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ rgb, int W, int H, int C, int fp16,
+                                                    void* __restrict__ feat) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= W * H) return;
+  const int x = p % W, y = p / W;
+  const float R = rgb[3 * p], G = rgb[3 * p + 1], B = rgb[3 * p + 2];
+  float gx = 0.f, gy = 0.f;
+  if (C == 5) {
+    const int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
+    const int yu = y > 0 ? y - 1 : 0, yd = y < H - 1 ? y + 1 : H - 1;
+    gx = 0.5f * (luma(rgb, y * W + xr) - luma(rgb, y * W + xl));
+    gy = 0.5f * (luma(rgb, yd * W + x) - luma(rgb, yu * W + x));
+  }
+  if (fp16) {
+    __half h[8] = {__float2half_rn(R), __float2half_rn(G), __float2half_rn(B), __float2half_rn(gx),
+                   __float2half_rn(gy), __float2half_rn(0.f), __float2half_rn(0.f), __float2half_rn(0.f)};
+    reinterpret_cast<uint4*>(feat)[p] = *reinterpret_cast<const uint4*>(h);
+  } else {
+    reinterpret_cast<float4*>(feat)[p] = make_float4(R, G, B, gx);
+    if (C == 5) reinterpret_cast<float*>(reinterpret_cast<float4*>(feat) + (size_t)W * H)[p] = gy;
+  }
+}
+
+hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s) {
+  const int n = P.W * P.H;
+  hipLaunchKernelGGL(k_features, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rgb, P.W, P.H, P.C, P.fp16,
+                     feat);
+  return hipGetLastError();
+}
+
+// Initial NNF: caller's offsets with targets clamped into the frame, or a
+// uniform random target per pixel from the Philox stream (phase 1, draw 0).
+__global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const int32_t* __restrict__ init0,
+                                                       const int32_t* __restrict__ init1) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int dir = blockIdx.y;
+  const int W = P.W, H = P.H;
+  if (p >= W * H) return;
+  const int x = p % W, y = p / W;
+  const int32_t* init = dir ? init1 : init0;
+  int tx, ty;
+  if (init) {
+    const int32_t v = init[p];
+    tx = clampi(x + off_dx(v), 0, W - 1);
+    ty = clampi(y + off_dy(v), 0, H - 1);
+  } else {
+    uint64_t c[4] = {(uint64_t)p, 0, 0, rng_word3(1, dir, 0, 0)};
+    philox4x64(c, P.seed, 0);
+    tx = draw_below(c[0], (uint32_t)W);
+    ty = draw_below(c[1], (uint32_t)H);
+  }
+  w.nnf[dir][p] = pack_off(tx - x, ty - y);
+  w.win[dir][p] = -1;
+  w.loss[dir][p] = __builtin_huge_val();
+  w.hlabel[dir][p] = -1;
+  w.twin[dir][p] = -1;
+  w.tloss[dir][p] = __builtin_huge_val();
+  w.cost[dir][p] = 0.f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < 8 && blockIdx.x == 0) w.counters[k] = 0;
+  if (k >= 2 * P.planes_per_dir) return;
+  const int dir = k / P.planes_per_dir;
+  int r = k - dir * P.planes_per_dir;
+  int level = 0;
+  while (level + 1 < P.n_levels && r >= P.plane_off[level + 1]) ++level;
+  r -= P.plane_off[level];
+  const int nb = P.nbx[level] * P.nby[level];
+  const int stage = r / nb + 1;
+  const int b = r % nb;
+  const int B = P.block[level];
+  msgpm_plane pl;
+  for (int i = 0; i < 9; ++i) pl.H[i] = 0.0;
+  pl.dir = dir;
+  pl.level = level;
+  pl.stage = stage;
+  pl.block = b;
+  pl.x0 = block_origin(P.W, B, b % P.nbx[level]);
+  pl.y0 = block_origin(P.H, B, b / P.nbx[level]);
+  pl.bw = B < P.W ? B : P.W;
+  pl.bh = B < P.H ? B : P.H;
+  pl.support = pl.count = 0;
+  pl.hyp = -1;
+  pl.hyp_count = 0;
+  pl.refit = pl.detected = pl.rk = pl.pass = pl.valid = pl.reserved = 0;
+  w.planes[k] = pl;
+}
+
+hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
+                             hipStream_t s) {
+  const int n = P.W * P.H;
+  hipLaunchKernelGGL(k_init_pixels, dim3((n + kBlock - 1) / kBlock, 2), dim3(kBlock), 0, s, P, w, init0, init1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int np = 2 * P.planes_per_dir;
+  const int nblk = (np > 8 ? np : 8);
+  hipLaunchKernelGGL(k_init_planes, dim3((nblk + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P, w);
+  return hipGetLastError();
+}
+
+}  // namespace msgpm

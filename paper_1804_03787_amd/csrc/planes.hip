@@ -1,0 +1,800 @@
+// Plane detection, assignment and forward-backward checks (FP64).
+//
+// Every floating-point decision here (RANSAC inlier tests, the DLT and its
+// least-squares refit, colour-consistency losses, forward-backward distances,
+// rounding to the pixel grid) is taken in FP64 with a fixed operation order and
+// no contraction, so that identical inputs give identical decisions on any
+// implementation that follows the same written steps:
+//   * Hartley normalisation: centroid = sum / n, mean distance = sum of
+//     sqrt(dx^2 + dy^2) / n, scale sqrt(2) / mean distance, coordinates
+//     s * (x - centroid);
+//   * 8x8 systems solved by Gaussian elimination with partial pivoting (first
+//     largest pivot, rejected below 1e-10), back substitution;
+//   * H = T_dst^-1 * Hn * T_src by plain 3x3 products, then divided by H[8];
+//   * the refit's normal-equation sums run over the inliers in point-list
+//     order, one accumulator per entry.
+#include "common.h"
+
+#include <hip/hip_fp16.h>
+
+#pragma clang fp contract(off)
+
+namespace msgpm {
+
+// ---------------------------------------------------------------------------
+// Shared FP64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline bool project(const double* H, double x, double y, double& qx, double& qy) {
+  const double w = H[6] * x + H[7] * y + H[8];
+  if (!(w > 0)) return false;
+  qx = (H[0] * x + H[1] * y + H[2]) / w;
+  qy = (H[3] * x + H[4] * y + H[5]) / w;
+  return true;
+}
+
+__device__ inline void rgb_at(const DevParams& P, const void* F, int idx, double* v) {
+  if (P.fp16) {
+    const uint4 u = reinterpret_cast<const uint4*>(F)[idx];
+    const float2 a = __half22float2(__builtin_bit_cast(__half2, u.x));
+    const float2 b = __half22float2(__builtin_bit_cast(__half2, u.y));
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+  } else {
+    const float4 a = reinterpret_cast<const float4*>(F)[idx];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+  }
+}
+
+// Colour-consistency error e(p, H): mean over RGB of the squared difference
+// between F1 at p and F2 bilinearly sampled at pi(H p) (Eq. 3 in squared RMS
+// form); +inf when pi(H p) is undefined or outside the frame.
+__device__ double colour_err(const DevParams& P, const Ws& w, int dir, int px, int py, const double* H) {
+  const int W = P.W, Hh = P.H;
+  double qx, qy;
+  if (!project(H, px, py, qx, qy)) return __builtin_huge_val();
+  if (qx < 0 || qx > W - 1 || qy < 0 || qy > Hh - 1) return __builtin_huge_val();
+  const double fx0 = floor(qx), fy0 = floor(qy);
+  int bx = (int)fx0, by = (int)fy0;
+  double fx = qx - fx0, fy = qy - fy0;
+  if (bx < 0) {
+    bx = 0;
+    fx = 0;
+  } else if (bx >= W - 1) {
+    bx = W - 1;
+    fx = 0;
+  }
+  if (by < 0) {
+    by = 0;
+    fy = 0;
+  } else if (by >= Hh - 1) {
+    by = Hh - 1;
+    fy = 0;
+  }
+  const int x1 = bx + 1 < W - 1 ? bx + 1 : W - 1;
+  const int y1 = by + 1 < Hh - 1 ? by + 1 : Hh - 1;
+  const void* F2 = w.feat[1 - dir];
+  double a[3], b[3], c[3], d[3], f1[3];
+  rgb_at(P, F2, by * W + bx, a);
+  rgb_at(P, F2, by * W + x1, b);
+  rgb_at(P, F2, y1 * W + bx, c);
+  rgb_at(P, F2, y1 * W + x1, d);
+  rgb_at(P, w.feat[dir], py * W + px, f1);
+  double e = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double v = (1 - fy) * ((1 - fx) * a[k] + fx * b[k]) + fy * ((1 - fx) * c[k] + fx * d[k]);
+    const double df = f1[k] - v;
+    e += df * df;
+  }
+  return e / 3.0;
+}
+
+// Forward-backward test of pixel p of direction dir under plane H against the
+// other direction's assignment `other`.
+__device__ bool fb_test(const DevParams& P, const Ws& w, int px, int py, const double* H, const int32_t* other) {
+  const int W = P.W, Hh = P.H;
+  double qx, qy;
+  if (!project(H, px, py, qx, qy)) return false;
+  if (qx < 0 || qx > W - 1 || qy < 0 || qy > Hh - 1) return false;
+  const int rx = clampi((int)floor(qx + 0.5), 0, W - 1);
+  const int ry = clampi((int)floor(qy + 0.5), 0, Hh - 1);
+  const int j = other[ry * W + rx];
+  if (j < 0) return false;
+  double bx, by;
+  if (!project(w.planes[j].H, qx, qy, bx, by)) return false;
+  const double d2 = (bx - px) * (bx - px) + (by - py) * (by - py);
+  return d2 < P.fb2;
+}
+
+// ---------------------------------------------------------------------------
+// Homography estimation
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ inline bool hartley_n(const double* x, const double* y, double& s, double& cx, double& cy) {
+  double sx = 0, sy = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    sx += x[i];
+    sy += y[i];
+  }
+  cx = sx / N;
+  cy = sy / N;
+  double md = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double ex = x[i] - cx, ey = y[i] - cy;
+    md += sqrt(ex * ex + ey * ey);
+  }
+  md = md / N;
+  if (!(md > 0)) return false;
+  s = sqrt(2.0) / md;
+  return true;
+}
+
+// Gaussian elimination with partial pivoting on an 8x8 system held in
+// registers; row exchanges are done with selects so indices stay static.
+__device__ inline bool gauss8(double (&A)[8][8], double (&b)[8], double (&x)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int piv = k;
+    double best = fabs(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < 8; ++i) {
+      const double a = fabs(A[i][k]);
+      if (a > best) {
+        best = a;
+        piv = i;
+      }
+    }
+    if (best < 1e-10) return false;
+#pragma unroll
+    for (int i = k + 1; i < 8; ++i) {
+      const bool sw = (i == piv);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double t = A[k][j];
+        A[k][j] = sw ? A[i][j] : A[k][j];
+        A[i][j] = sw ? t : A[i][j];
+      }
+      const double t = b[k];
+      b[k] = sw ? b[i] : b[k];
+      b[i] = sw ? t : b[i];
+    }
+#pragma unroll
+    for (int i = k + 1; i < 8; ++i) {
+      const double f = A[i][k] / A[k][k];
+#pragma unroll
+      for (int j = k; j < 8; ++j) A[i][j] -= f * A[k][j];
+      b[i] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int i = 7; i >= 0; --i) {
+    double s = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 8; ++j) s -= A[i][j] * x[j];
+    x[i] = s / A[i][i];
+  }
+  return true;
+}
+
+__device__ inline bool denormalise(const double (&h)[8], double s1, double c1x, double c1y, double s2, double c2x,
+                                   double c2y, double* Hout) {
+  const double Hn[9] = {h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], 1.0};
+  const double Ts[9] = {s1, 0, -s1 * c1x, 0, s1, -s1 * c1y, 0, 0, 1};
+  const double Ti[9] = {1.0 / s2, 0, c2x, 0, 1.0 / s2, c2y, 0, 0, 1};
+  double M[9], R[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += Hn[i * 3 + k] * Ts[k * 3 + j];
+      M[i * 3 + j] = t;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += Ti[i * 3 + k] * M[k * 3 + j];
+      R[i * 3 + j] = t;
+    }
+  if (fabs(R[8]) < 1e-12) return false;
+  const double d = R[8];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hout[i] = R[i] / d;
+  return true;
+}
+
+// Normalised 4-point DLT with H[8] = 1.
+__device__ inline bool dlt4(const double (&sx)[4], const double (&sy)[4], const double (&dx)[4],
+                            const double (&dy)[4], double* Hout) {
+  double s1, c1x, c1y, s2, c2x, c2y;
+  if (!hartley_n<4>(sx, sy, s1, c1x, c1y)) return false;
+  if (!hartley_n<4>(dx, dy, s2, c2x, c2y)) return false;
+  double A[8][8], b[8], h[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double x = s1 * (sx[i] - c1x), y = s1 * (sy[i] - c1y);
+    const double u = s2 * (dx[i] - c2x), v = s2 * (dy[i] - c2y);
+    A[2 * i][0] = x;
+    A[2 * i][1] = y;
+    A[2 * i][2] = 1;
+    A[2 * i][3] = 0;
+    A[2 * i][4] = 0;
+    A[2 * i][5] = 0;
+    A[2 * i][6] = -x * u;
+    A[2 * i][7] = -y * u;
+    A[2 * i + 1][0] = 0;
+    A[2 * i + 1][1] = 0;
+    A[2 * i + 1][2] = 0;
+    A[2 * i + 1][3] = x;
+    A[2 * i + 1][4] = y;
+    A[2 * i + 1][5] = 1;
+    A[2 * i + 1][6] = -x * v;
+    A[2 * i + 1][7] = -y * v;
+    b[2 * i] = u;
+    b[2 * i + 1] = v;
+  }
+  if (!gauss8(A, b, h)) return false;
+  return denormalise(h, s1, c1x, c1y, s2, c2x, c2y, Hout);
+}
+
+// Reprojection inlier test, division-free: w > 0 and |(u, v) - w q|^2 < tau^2 w^2.
+__device__ inline bool ransac_inlier(const double* H, double x, double y, double qx, double qy, double tau2) {
+  const double w = H[6] * x + H[7] * y + H[8];
+  if (!(w > 0)) return false;
+  const double u = H[0] * x + H[1] * y + H[2];
+  const double v = H[3] * x + H[4] * y + H[5];
+  const double ex = u - w * qx, ey = v - w * qy;
+  const double e2 = ex * ex + ey * ey;
+  const double t = tau2 * w * w;
+  return e2 < t;
+}
+
+__device__ inline bool collinear(int ax, int ay, int bx, int by, int cx, int cy) {
+  return (long long)(bx - ax) * (cy - ay) - (long long)(by - ay) * (cx - ax) == 0;
+}
+
+__device__ inline uint32_t pack_pt(int x, int y) { return (uint32_t)x | ((uint32_t)y << 16); }
+__device__ inline int pt_x(uint32_t v) { return (int)(v & 0xffffu); }
+__device__ inline int pt_y(uint32_t v) { return (int)(v >> 16); }
+
+// ---------------------------------------------------------------------------
+// RANSAC: one workgroup per (window, direction).  Points live in LDS; each
+// thread draws, solves and scores its own hypotheses against all points.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int s_wave[kBlock / kWave];
+  __shared__ int s_n;
+  __shared__ unsigned long long s_key[kBlock / kWave];
+  __shared__ double s_H[9], s_Hr[9];
+  __shared__ double s_sum[8];
+  __shared__ double s_N[64], s_rhs[8];
+  __shared__ int s_ok, s_cnt, s_ni;
+
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int b = blockIdx.x, dir = blockIdx.y;
+  const int W = P.W, Hh = P.H;
+  const int B = P.block[level], nbx = P.nbx[level];
+  const int bw = B < W ? B : W, bh = B < Hh ? B : Hh;
+  const int x0 = block_origin(W, B, b % nbx), y0 = block_origin(Hh, B, b / nbx);
+  const int nmax = bw * bh;
+  uint32_t* src = smem;
+  uint32_t* dst = smem + nmax;
+  uint8_t* flag = reinterpret_cast<uint8_t*>(smem + 2 * nmax);
+  msgpm_plane* pl = &w.planes[plane_index(P, dir, level, stage, b)];
+  const int32_t* nnf = w.nnf[dir];
+  const int32_t* win = w.win[dir];
+
+  // point list (row-major in the window; stage 2 keeps the unassigned pixels)
+  if (t == 0) s_n = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nmax; c0 += kBlock) {
+    const int i = c0 + t;
+    int x = 0, y = 0, p = 0;
+    bool keep = i < nmax;
+    if (keep) {
+      x = x0 + i % bw;
+      y = y0 + i / bw;
+      p = y * W + x;
+      if (stage == 2) keep = win[p] < 0;
+    }
+    const unsigned long long m = __ballot(keep);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wave] = __popcll(m);
+    __syncthreads();
+    int off = s_n;
+    for (int k = 0; k < wave; ++k) off += s_wave[k];
+    if (keep) {
+      const int32_t v = nnf[p];
+      src[off + before] = pack_pt(x, y);
+      dst[off + before] = pack_pt(x + off_dx(v), y + off_dy(v));
+    }
+    __syncthreads();
+    if (t == 0) s_n += s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
+  }
+  const int n = s_n;
+  const int mmin_frac = (int)ceil(P.mu * (double)bw * (double)bh);
+  const int mmin = mmin_frac > P.m_min_abs ? mmin_frac : P.m_min_abs;
+
+  msgpm_plane out;
+  for (int i = 0; i < 9; ++i) out.H[i] = 0.0;
+  out.dir = dir;
+  out.level = level;
+  out.stage = stage;
+  out.block = b;
+  out.x0 = x0;
+  out.y0 = y0;
+  out.bw = bw;
+  out.bh = bh;
+  out.support = n;
+  out.count = 0;
+  out.hyp = -1;
+  out.hyp_count = 0;
+  out.refit = out.detected = out.rk = out.pass = out.valid = out.reserved = 0;
+  if (n < mmin || n < 4) {
+    if (t == 0) *pl = out;
+    return;
+  }
+
+  // hypotheses h = t, t + 256, ...: draw 4 points (partial Fisher-Yates over a
+  // virtual identity permutation), reject degenerate samples, solve, count
+  const double tau2 = P.tau2;
+  const uint64_t w3 = rng_word3(3, dir, level + 1, stage);
+  int my_cnt = -1, my_h = -1;
+  double myH[9];
+  for (int i = 0; i < 9; ++i) myH[i] = 0.0;
+  for (int h = t; h < P.hyps; h += kBlock) {
+    uint64_t c[4] = {(uint64_t)b, (uint64_t)h, 0, w3};
+    philox4x64(c, P.seed, 0);
+    int key[8], val[8], nm = 0, sel[4];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) key[m] = val[m] = -1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rj = j + draw_below(c[j], (uint32_t)(n - j));
+      int vj = j, vr = rj, fj = -1, fr = -1;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        if (m < nm && key[m] == j) {
+          vj = val[m];
+          fj = m;
+        }
+        if (m < nm && key[m] == rj) {
+          vr = val[m];
+          fr = m;
+        }
+      }
+      if (fj < 0) fj = nm++;
+      if (fr < 0) fr = nm++;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        if (m == fj) {
+          key[m] = j;
+          val[m] = vr;
+        }
+        if (m == fr) {
+          key[m] = rj;
+          val[m] = vj;
+        }
+      }
+      sel[j] = vr;
+    }
+    int SX[4], SY[4], DX[4], DY[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a = src[sel[j]], d = dst[sel[j]];
+      SX[j] = pt_x(a);
+      SY[j] = pt_y(a);
+      DX[j] = pt_x(d);
+      DY[j] = pt_y(d);
+    }
+    bool degen = false;
+    degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[2], SY[2]);
+    degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[3], SY[3]);
+    degen = degen || collinear(SX[0], SY[0], SX[2], SY[2], SX[3], SY[3]);
+    degen = degen || collinear(SX[1], SY[1], SX[2], SY[2], SX[3], SY[3]);
+    degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[2], DY[2]);
+    degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[3], DY[3]);
+    degen = degen || collinear(DX[0], DY[0], DX[2], DY[2], DX[3], DY[3]);
+    degen = degen || collinear(DX[1], DY[1], DX[2], DY[2], DX[3], DY[3]);
+    if (degen) continue;
+    const double sx[4] = {(double)SX[0], (double)SX[1], (double)SX[2], (double)SX[3]};
+    const double sy[4] = {(double)SY[0], (double)SY[1], (double)SY[2], (double)SY[3]};
+    const double ddx[4] = {(double)DX[0], (double)DX[1], (double)DX[2], (double)DX[3]};
+    const double ddy[4] = {(double)DY[0], (double)DY[1], (double)DY[2], (double)DY[3]};
+    double Hh_[9];
+    if (!dlt4(sx, sy, ddx, ddy, Hh_)) continue;
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+      const uint32_t a = src[i], d = dst[i];
+      cnt += ransac_inlier(Hh_, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
+    }
+    if (cnt > my_cnt) {
+      my_cnt = cnt;
+      my_h = h;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) myH[i] = Hh_[i];
+    }
+  }
+  // winner: largest count, lowest hypothesis index on ties
+  unsigned long long key = my_cnt >= 0 ? (((unsigned long long)my_cnt << 32) | (0xffffffffu - (unsigned)my_h)) : 0ull;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long other = __shfl_xor(key, o);
+    key = other > key ? other : key;
+  }
+  if (lane == 0) s_key[wave] = key;
+  __syncthreads();
+  unsigned long long best = s_key[0];
+  for (int k = 1; k < kBlock / kWave; ++k) best = s_key[k] > best ? s_key[k] : best;
+  if (best == 0ull) {
+    if (t == 0) *pl = out;
+    return;
+  }
+  const int best_cnt = (int)(best >> 32);
+  const int best_h = (int)(0xffffffffu - (unsigned)(best & 0xffffffffu));
+  if (my_h == best_h && my_cnt >= 0) {
+    for (int i = 0; i < 9; ++i) s_H[i] = myH[i];
+  }
+  if (t == 0) {
+    s_cnt = 0;
+    s_ni = 0;
+  }
+  __syncthreads();
+
+  // least-squares refit on the winner's inliers
+  int local_ni = 0;
+  for (int i = t; i < n; i += kBlock) {
+    const uint32_t a = src[i], d = dst[i];
+    const bool in = ransac_inlier(s_H, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
+    flag[i] = in ? 1 : 0;
+    local_ni += in;
+  }
+  atomicAdd(&s_ni, local_ni);
+  __syncthreads();
+  const int ni = s_ni;
+  // centroids (lanes 0-3), in point-list order over the inliers
+  if (t < 4) {
+    double acc = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!flag[i]) continue;
+      const uint32_t v = (t < 2) ? src[i] : dst[i];
+      acc += (double)((t & 1) ? pt_y(v) : pt_x(v));
+    }
+    s_sum[t] = acc;
+  }
+  __syncthreads();
+  const double c1x = s_sum[0] / ni, c1y = s_sum[1] / ni, c2x = s_sum[2] / ni, c2y = s_sum[3] / ni;
+  if (t < 2) {
+    const double cx = t ? c2x : c1x, cy = t ? c2y : c1y;
+    double md = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!flag[i]) continue;
+      const uint32_t v = t ? dst[i] : src[i];
+      const double ex = (double)pt_x(v) - cx, ey = (double)pt_y(v) - cy;
+      md += sqrt(ex * ex + ey * ey);
+    }
+    s_sum[4 + t] = md;
+  }
+  __syncthreads();
+  const double md1 = s_sum[4] / ni, md2 = s_sum[5] / ni;
+  const bool norm_ok = ni >= 4 && (md1 > 0) && (md2 > 0);
+  const double s1 = sqrt(2.0) / md1, s2 = sqrt(2.0) / md2;
+  if (norm_ok && t < 44) {
+    // entry t: t < 36 -> N[j][k] with j <= k (row-major upper triangle); else rhs[t - 36]
+    int j = 0, k = 0;
+    if (t < 36) {
+      int r = t;
+      while (r >= 8 - j) {
+        r -= 8 - j;
+        ++j;
+      }
+      k = j + r;
+    } else {
+      j = t - 36;
+    }
+    double acc = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!flag[i]) continue;
+      const uint32_t a = src[i], d = dst[i];
+      const double x = s1 * ((double)pt_x(a) - c1x), y = s1 * ((double)pt_y(a) - c1y);
+      const double u = s2 * ((double)pt_x(d) - c2x), v = s2 * ((double)pt_y(d) - c2y);
+      const double a0[8] = {x, y, 1, 0, 0, 0, -x * u, -y * u};
+      const double a1[8] = {0, 0, 0, x, y, 1, -x * v, -y * v};
+      if (t < 36) {
+        acc += a0[j] * a0[k];
+        acc += a1[j] * a1[k];
+      } else {
+        acc += a0[j] * u;
+        acc += a1[j] * v;
+      }
+    }
+    if (t < 36) {
+      s_N[j * 8 + k] = acc;
+      s_N[k * 8 + j] = acc;
+    } else {
+      s_rhs[j] = acc;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    s_ok = 0;
+    if (norm_ok) {
+      double A[8][8], rhs[8], h[8];
+      for (int r = 0; r < 8; ++r) {
+        rhs[r] = s_rhs[r];
+        for (int q = 0; q < 8; ++q) A[r][q] = s_N[r * 8 + q];
+      }
+      double Hr[9];
+      if (gauss8(A, rhs, h) && denormalise(h, s1, c1x, c1y, s2, c2x, c2y, Hr)) {
+        for (int i = 0; i < 9; ++i) s_Hr[i] = Hr[i];
+        s_ok = 1;
+      }
+    }
+  }
+  __syncthreads();
+  int final_cnt = best_cnt;
+  bool use_refit = false;
+  if (s_ok) {
+    int local = 0;
+    for (int i = t; i < n; i += kBlock) {
+      const uint32_t a = src[i], d = dst[i];
+      local += ransac_inlier(s_Hr, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
+    }
+    atomicAdd(&s_cnt, local);
+    __syncthreads();
+    if (s_cnt >= best_cnt) {
+      use_refit = true;
+      final_cnt = s_cnt;
+    }
+  }
+  if (t == 0) {
+    for (int i = 0; i < 9; ++i) out.H[i] = use_refit ? s_Hr[i] : s_H[i];
+    out.hyp = best_h;
+    out.hyp_count = best_cnt;
+    out.count = final_cnt;
+    out.refit = use_refit ? 1 : 0;
+    out.detected = final_cnt >= mmin ? 1 : 0;
+    out.valid = out.detected;
+    *pl = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assignment: per pixel, the minimum of the key (L, level, stage, window) over
+// the incumbent and the inlier planes of (level, stage) whose window covers p.
+// ---------------------------------------------------------------------------
+__device__ inline bool key_less(double L1, const msgpm_plane& a, double L2, const msgpm_plane& b) {
+  if (L1 != L2) return L1 < L2;
+  if (a.level != b.level) return a.level < b.level;
+  if (a.stage != b.stage) return a.stage < b.stage;
+  return a.block < b.block;
+}
+
+__global__ __launch_bounds__(kBlock) void k_assign(DevParams P, Ws w, int level, int stage, int tentative) {
+  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+  const int W = P.W, Hh = P.H;
+  if (p >= W * Hh) return;
+  const int x = p % W, y = p / W;
+  int bwin = w.win[dir][p];
+  double bl = w.loss[dir][p];
+  if (stage == 1 || bwin < 0) {
+    const int B = P.block[level], nbx = P.nbx[level], nby = P.nby[level];
+    int xlo, xhi, ylo, yhi;
+    cover_range(W, B, nbx, x, xlo, xhi);
+    cover_range(Hh, B, nby, y, ylo, yhi);
+    for (int by = ylo; by <= yhi; ++by)
+      for (int bx = xlo; bx <= xhi; ++bx) {
+        const int k = plane_index(P, dir, level, stage, by * nbx + bx);
+        const msgpm_plane& pk = w.planes[k];
+        if (!(tentative ? pk.detected : pk.valid)) continue;
+        const double e = colour_err(P, w, dir, x, y, pk.H);
+        if (!(e < P.eps2)) continue;
+        if (bwin < 0 || key_less(e, pk, bl, w.planes[bwin])) {
+          bwin = k;
+          bl = e;
+        }
+      }
+  }
+  int32_t* ow = tentative ? w.twin[dir] : w.win[dir];
+  double* ol = tentative ? w.tloss[dir] : w.loss[dir];
+  ow[p] = bwin;
+  ol[p] = bwin >= 0 ? bl : __builtin_huge_val();
+}
+
+// ---------------------------------------------------------------------------
+// Plane symmetry: one workgroup per (window, direction).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_symmetry(DevParams P, Ws w, int level, int stage) {
+  __shared__ int s_rk, s_pass;
+  const int t = threadIdx.x, b = blockIdx.x, dir = blockIdx.y;
+  msgpm_plane* pl = &w.planes[plane_index(P, dir, level, stage, b)];
+  if (t == 0) {
+    s_rk = 0;
+    s_pass = 0;
+  }
+  __syncthreads();
+  if (!pl->detected) {
+    if (t == 0) {
+      pl->rk = 0;
+      pl->pass = 0;
+      pl->valid = 0;
+    }
+    return;
+  }
+  const int W = P.W;
+  const int x0 = pl->x0, y0 = pl->y0, bw = pl->bw, bh = pl->bh;
+  double H[9];
+  for (int i = 0; i < 9; ++i) H[i] = pl->H[i];
+  const int32_t* other = w.twin[1 - dir];
+  int rk = 0, pass = 0;
+  for (int i = t; i < bw * bh; i += kBlock) {
+    const int x = x0 + i % bw, y = y0 + i / bw;
+    if (stage == 2 && w.win[dir][y * W + x] >= 0) continue;
+    const double e = colour_err(P, w, dir, x, y, H);
+    if (e < P.eps2) {
+      ++rk;
+      pass += fb_test(P, w, x, y, H, other) ? 1 : 0;
+    }
+  }
+  atomicAdd(&s_rk, rk);
+  atomicAdd(&s_pass, pass);
+  __syncthreads();
+  if (t == 0) {
+    const int mmin_frac = (int)ceil(P.mu * (double)bw * (double)bh);
+    const int mmin = mmin_frac > P.m_min_abs ? mmin_frac : P.m_min_abs;
+    pl->rk = s_rk;
+    pl->pass = s_pass;
+    pl->valid = (s_rk >= mmin && (long long)s_pass * P.eta_den > (long long)P.eta_num * s_rk) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// End-of-level forward-backward check (Jacobi over both directions).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_fb(DevParams P, Ws w) {
+  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+  if (p >= P.W * P.H) return;
+  const int j = w.win[dir][p];
+  int o = j;
+  double l = w.loss[dir][p];
+  if (j >= 0 && !fb_test(P, w, p % P.W, p / P.W, w.planes[j].H, w.win[1 - dir])) {
+    o = -1;
+    l = __builtin_huge_val();
+  }
+  w.twin[dir][p] = o;
+  w.tloss[dir][p] = l;
+}
+
+__global__ __launch_bounds__(kBlock) void k_commit(DevParams P, Ws w) {
+  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+  if (p >= P.W * P.H) return;
+  w.win[dir][p] = w.twin[dir][p];
+  w.loss[dir][p] = w.tloss[dir][p];
+}
+
+// ---------------------------------------------------------------------------
+// NNF update from assigned planes and region plane choice.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_nnf_update(DevParams P, Ws w, int level) {
+  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+  const int W = P.W, Hh = P.H;
+  if (p >= W * Hh) return;
+  const int x = p % W, y = p / W;
+  const int j = w.win[dir][p];
+  if (j >= 0) {
+    double qx, qy;
+    if (project(w.planes[j].H, x, y, qx, qy)) {
+      const int rx = clampi((int)floor(qx + 0.5), 0, W - 1);
+      const int ry = clampi((int)floor(qy + 0.5), 0, Hh - 1);
+      w.nnf[dir][p] = pack_off(rx - x, ry - y);
+    }
+  }
+  const int B = P.block[level], nbx = P.nbx[level], nby = P.nby[level];
+  int xlo, xhi, ylo, yhi;
+  cover_range(W, B, nbx, x, xlo, xhi);
+  cover_range(Hh, B, nby, y, ylo, yhi);
+  int best = -1, bestc = -1;
+  for (int stage = 1; stage <= 2; ++stage)
+    for (int by = ylo; by <= yhi; ++by)
+      for (int bx = xlo; bx <= xhi; ++bx) {
+        const int k = plane_index(P, dir, level, stage, by * nbx + bx);
+        const msgpm_plane& pk = w.planes[k];
+        if (!pk.valid) continue;
+        if (pk.count > bestc) {
+          bestc = pk.count;
+          best = k;
+        }
+      }
+  if (best >= 0) w.hlabel[dir][p] = best;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(DevParams P, Ws w, float* flow0, float* flow1, uint8_t* occ0,
+                                                    uint8_t* occ1) {
+  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+  const int W = P.W;
+  if (p >= W * P.H) return;
+  const int x = p % W, y = p / W;
+  float* flow = dir ? flow1 : flow0;
+  uint8_t* occ = dir ? occ1 : occ0;
+  const int j = w.win[dir][p];
+  double qx, qy;
+  if (j >= 0 && project(w.planes[j].H, x, y, qx, qy)) {
+    if (flow) {
+      flow[2 * p] = (float)(qx - x);
+      flow[2 * p + 1] = (float)(qy - y);
+    }
+    if (occ) occ[p] = 0;
+  } else {
+    const int32_t v = w.nnf[dir][p];
+    if (flow) {
+      flow[2 * p] = (float)off_dx(v);
+      flow[2 * p + 1] = (float)off_dy(v);
+    }
+    if (occ) occ[p] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static dim3 pixel_grid(const DevParams& P) { return dim3((P.W * P.H + kBlock - 1) / kBlock, 2); }
+
+size_t ransac_smem_bytes(const DevParams& P, int level) {
+  const int B = P.block[level];
+  const int bw = B < P.W ? B : P.W, bh = B < P.H ? B : P.H;
+  const size_t n = (size_t)bw * bh;
+  return 2 * n * sizeof(uint32_t) + ((n + 15) & ~(size_t)15);
+}
+
+hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s) {
+  const size_t sm = ransac_smem_bytes(P, level);
+  if (sm > 64 * 1024) {
+    // windows above 64x64 keep their point list in more than 64 KB of LDS
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ransac),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ransac, dim3(P.nbx[level] * P.nby[level], 2), dim3(kBlock), sm, s, P, w, level, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign(const DevParams& P, const Ws& w, int level, int stage, int tentative, hipStream_t s) {
+  hipLaunchKernelGGL(k_assign, pixel_grid(P), dim3(kBlock), 0, s, P, w, level, stage, tentative);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetry, dim3(P.nbx[level] * P.nby[level], 2), dim3(kBlock), 0, s, P, w, level, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_fb, pixel_grid(P), dim3(kBlock), 0, s, P, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_commit, pixel_grid(P), dim3(kBlock), 0, s, P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s) {
+  hipLaunchKernelGGL(k_nnf_update, pixel_grid(P), dim3(kBlock), 0, s, P, w, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
+                           uint8_t* occ1, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, pixel_grid(P), dim3(kBlock), 0, s, P, w, flow0, flow1, occ0, occ1);
+  return hipGetLastError();
+}
+
+}  // namespace msgpm

@@ -1,0 +1,268 @@
+"""Python binding of libmsgpm (C ABI in include/msgpm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libmsgpm.so.  PyTorch supplies device memory (the workspace and frame
+buffers) and the current HIP stream.  There is no fallback: if the library is
+not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsgpm.so")
+MAX_LEVELS = 8
+FLAG_FP16 = 1
+
+STATUS = {0: "OK", 1: "E_INVALID", 3: "E_DEVICE", 4: "E_UNSUPPORTED"}
+
+
+class MsgpmError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("channels", ctypes.c_int32),
+        ("patch_radius", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("block", ctypes.c_int32 * MAX_LEVELS),
+        ("pm_iters", ctypes.c_int32), ("ransac_hyps", ctypes.c_int32), ("search_radius0", ctypes.c_int32),
+        ("min_support_abs", ctypes.c_int32), ("eta_num", ctypes.c_int32), ("eta_den", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("grad_weight", ctypes.c_double), ("inlier_px", ctypes.c_double), ("eps_color", ctypes.c_double),
+        ("fb_px", ctypes.c_double), ("min_support_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+    ]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [
+        ("total_bytes", ctypes.c_uint64), ("feat", ctypes.c_uint64 * 2), ("feat_bytes", ctypes.c_uint64),
+        ("nnf", ctypes.c_uint64 * 2), ("cost", ctypes.c_uint64 * 2), ("win", ctypes.c_uint64 * 2),
+        ("loss", ctypes.c_uint64 * 2), ("hlabel", ctypes.c_uint64 * 2), ("twin", ctypes.c_uint64 * 2),
+        ("tloss", ctypes.c_uint64 * 2), ("planes", ctypes.c_uint64), ("counters", ctypes.c_uint64),
+        ("n_planes", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+        ("level_blocks", ctypes.c_int32 * MAX_LEVELS), ("level_nbx", ctypes.c_int32 * MAX_LEVELS),
+    ]
+
+
+PLANE_INT_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "support", "count", "hyp",
+                    "hyp_count", "refit", "detected", "rk", "pass", "valid", "reserved"]
+PLANE_DTYPE = np.dtype([("H", "<f8", (9,))] + [(f, "<i4") for f in PLANE_INT_FIELDS])
+assert PLANE_DTYPE.itemsize == 144
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1804_03787_amd.build` "
+                               "(the HIP library is required: there is no CPU path)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(Params)
+        vp, i = ctypes.c_void_p, ctypes.c_int
+        sigs = {
+            "msgpm_layout_query": [P, ctypes.POINTER(Layout)],
+            "msgpm_solve": [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "msgpm_features": [P, vp, vp, vp, vp],
+            "msgpm_init_state": [P, vp, vp, vp, vp],
+            "msgpm_eval_cost": [P, vp, i, vp],
+            "msgpm_pm_halfsweep": [P, vp, i, i, i, i, vp],
+            "msgpm_ransac": [P, vp, i, i, vp],
+            "msgpm_assign": [P, vp, i, i, i, vp],
+            "msgpm_symmetry": [P, vp, i, i, vp],
+            "msgpm_fb_unassign": [P, vp, vp],
+            "msgpm_nnf_update": [P, vp, i, vp],
+            "msgpm_finalize": [P, vp, vp, vp, vp, vp, vp],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.msgpm_last_error.restype = ctypes.c_char_p
+        L.msgpm_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != 0:
+        raise MsgpmError(name, st, lib().msgpm_last_error().decode())
+
+
+def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 32, 16), iters: int = 8,
+                hyps: int = 256, R0: int = 0, tau: float = 1.0, eps: float = 0.1, tau_fb: float = 1.0,
+                mu: float = 0.25, m_min_abs: int = 8, eta=(1, 2), seed: int = 0, fp16: bool = False,
+                grad_weight: float = 1.0) -> Params:
+    p = Params()
+    p.width, p.height, p.channels, p.patch_radius = width, height, C, r
+    blocks = list(blocks)
+    p.n_levels = len(blocks)
+    for k, b in enumerate(blocks):
+        p.block[k] = b
+    p.pm_iters, p.ransac_hyps, p.search_radius0, p.min_support_abs = iters, hyps, R0, m_min_abs
+    p.eta_num, p.eta_den = eta
+    p.flags = FLAG_FP16 if fp16 else 0
+    p.grad_weight, p.inlier_px, p.eps_color, p.fb_px, p.min_support_frac = grad_weight, tau, eps, tau_fb, mu
+    p.seed = seed
+    return p
+
+
+def layout(p: Params) -> Layout:
+    L = Layout()
+    _call("msgpm_layout_query", ctypes.byref(p), ctypes.byref(L))
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Pair:
+    """Device state of one frame pair (one workspace) and the phase calls on it."""
+
+    def __init__(self, width: int, height: int, device="cuda", **params):
+        self.W, self.H = width, height
+        self.p = make_params(width, height, **params)
+        self.L = layout(self.p)
+        self.device = torch.device(device)
+        self.ws = torch.zeros(int(self.L.total_bytes), dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        self.n_planes = int(self.L.n_planes)
+
+    # ---- views of the workspace -------------------------------------------
+    def _view(self, off, count, dtype):
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[int(off):int(off) + nbytes].view(dtype)
+
+    def nnf(self, d):
+        return self._view(self.L.nnf[d], self.W * self.H, torch.int32)
+
+    def cost(self, d):
+        return self._view(self.L.cost[d], self.W * self.H, torch.float32)
+
+    def win(self, d):
+        return self._view(self.L.win[d], self.W * self.H, torch.int32)
+
+    def loss(self, d):
+        return self._view(self.L.loss[d], self.W * self.H, torch.float64)
+
+    def hlabel(self, d):
+        return self._view(self.L.hlabel[d], self.W * self.H, torch.int32)
+
+    def twin(self, d):
+        return self._view(self.L.twin[d], self.W * self.H, torch.int32)
+
+    def tloss(self, d):
+        return self._view(self.L.tloss[d], self.W * self.H, torch.float64)
+
+    def feat_bytes(self, f):
+        return self.ws[int(self.L.feat[f]):int(self.L.feat[f]) + int(self.L.feat_bytes)]
+
+    def planes_bytes(self):
+        return self.ws[int(self.L.planes):int(self.L.planes) + self.n_planes * PLANE_DTYPE.itemsize]
+
+    def planes(self) -> np.ndarray:
+        return self.planes_bytes().cpu().numpy().view(PLANE_DTYPE).copy()
+
+    def set_planes(self, arr: np.ndarray):
+        assert arr.dtype == PLANE_DTYPE and len(arr) == self.n_planes
+        self.planes_bytes().copy_(torch.from_numpy(arr.view(np.uint8).copy()).to(self.device))
+
+    def counters(self) -> np.ndarray:
+        return self._view(self.L.counters, 8, torch.int64).cpu().numpy().astype(np.uint64)
+
+    def features(self, f) -> np.ndarray:
+        """Features of frame f as (H, W, C) float32 on the host."""
+        n = self.W * self.H
+        C = self.p.channels
+        raw = self.feat_bytes(f)
+        if self.p.flags & FLAG_FP16:
+            h = raw[:n * 16].view(torch.float16).reshape(n, 8).float().cpu().numpy()
+            return h[:, :C].reshape(self.H, self.W, C)
+        a = raw[:n * 16].view(torch.float32).reshape(n, 4).cpu().numpy()
+        out = np.zeros((n, C), np.float32)
+        out[:, :3] = a[:, :3]
+        if C == 5:
+            out[:, 3] = a[:, 3]
+            out[:, 4] = raw[n * 16:n * 20].view(torch.float32).cpu().numpy()
+        return out.reshape(self.H, self.W, C)
+
+    # ---- phases --------------------------------------------------------------
+    def _frame(self, f):
+        t = torch.as_tensor(f)
+        assert t.shape == (self.H, self.W, 3)
+        return t.to(self.device, torch.float32).contiguous()
+
+    def set_features(self, rgb1, rgb2):
+        a, b = self._frame(rgb1), self._frame(rgb2)
+        self._keep = (a, b)
+        _call("msgpm_features", ctypes.byref(self.p), _ptr(a), _ptr(b), _ptr(self.ws), _stream())
+
+    def init_state(self, init0=None, init1=None):
+        i0 = None if init0 is None else torch.as_tensor(init0).to(self.device, torch.int32).contiguous()
+        i1 = None if init1 is None else torch.as_tensor(init1).to(self.device, torch.int32).contiguous()
+        _call("msgpm_init_state", ctypes.byref(self.p), _ptr(i0), _ptr(i1), _ptr(self.ws), _stream())
+
+    def eval_cost(self, mode):
+        _call("msgpm_eval_cost", ctypes.byref(self.p), _ptr(self.ws), mode, _stream())
+
+    def pm_halfsweep(self, colour, it, slot, restricted):
+        _call("msgpm_pm_halfsweep", ctypes.byref(self.p), _ptr(self.ws), colour, it, slot, int(restricted),
+              _stream())
+
+    def ransac(self, level, stage):
+        _call("msgpm_ransac", ctypes.byref(self.p), _ptr(self.ws), level, stage, _stream())
+
+    def assign(self, level, stage, tentative):
+        _call("msgpm_assign", ctypes.byref(self.p), _ptr(self.ws), level, stage, int(tentative), _stream())
+
+    def symmetry(self, level, stage):
+        _call("msgpm_symmetry", ctypes.byref(self.p), _ptr(self.ws), level, stage, _stream())
+
+    def fb_unassign(self):
+        _call("msgpm_fb_unassign", ctypes.byref(self.p), _ptr(self.ws), _stream())
+
+    def nnf_update(self, level):
+        _call("msgpm_nnf_update", ctypes.byref(self.p), _ptr(self.ws), level, _stream())
+
+    def finalize(self):
+        flows = [torch.empty((self.H, self.W, 2), dtype=torch.float32, device=self.device) for _ in range(2)]
+        occs = [torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device) for _ in range(2)]
+        _call("msgpm_finalize", ctypes.byref(self.p), _ptr(self.ws), _ptr(flows[0]), _ptr(flows[1]),
+              _ptr(occs[0]), _ptr(occs[1]), _stream())
+        return flows, occs
+
+    def solve(self, rgb1, rgb2, init0=None, init1=None, out=None):
+        """Whole pipeline; returns ([flow0, flow1], [occ0, occ1]) as device tensors."""
+        a, b = self._frame(rgb1), self._frame(rgb2)
+        i0 = None if init0 is None else torch.as_tensor(init0).to(self.device, torch.int32).contiguous()
+        i1 = None if init1 is None else torch.as_tensor(init1).to(self.device, torch.int32).contiguous()
+        if out is None:
+            flows = [torch.empty((self.H, self.W, 2), dtype=torch.float32, device=self.device) for _ in range(2)]
+            occs = [torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device) for _ in range(2)]
+        else:
+            flows, occs = out
+        _call("msgpm_solve", ctypes.byref(self.p), _ptr(a), _ptr(b), _ptr(i0), _ptr(i1), _ptr(self.ws),
+              _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _stream())
+        self._keep = (a, b, i0, i1)
+        return flows, occs
+
+
+def solve(frame1, frame2, **params):
+    """One-shot solve of a frame pair (numpy or torch HWC float32 frames)."""
+    H, W = frame1.shape[:2]
+    pair = Pair(W, H, **params)
+    flows, occs = pair.solve(frame1, frame2)
+    return pair, flows, occs

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs, through the C ABI.
+
+Phase-isolated ("lock-step") tests feed the oracle's exact state to each GPU
+phase and compare the phase's outputs:
+  * integer, index and FP64 outputs (features, initial NNF, RANSAC plane
+    records, assignments, symmetry counts, FB, NNF update, flow of assigned
+    pixels) must be bit-exact;
+  * PatchMatch offsets must be bit-exact except at pixels the oracle flags as
+    near-ties (a cost comparison within 1e-5 relative); FP32 costs must agree
+    within 1e-5 relative plus 1e-7 (2r+1)^2 C absolute.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_03787_amd import synth
+from tests import parity
+from tests.conftest import TINY_PARAMS
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_03787_amd import msgpm
+    msgpm.lib()
+    return msgpm
+
+
+def _gpu_params(p):
+    keys = ("C", "r", "blocks", "iters", "hyps", "R0", "tau", "eps", "tau_fb", "mu", "m_min_abs", "eta", "seed",
+            "fp16", "grad_weight")
+    full = dict(oracle.DEFAULTS)
+    full.update(p)
+    return {k: full[k] for k in keys}
+
+
+RAGGED = dict(C=3, r=2, grad_weight=0.0, blocks=(20, 12), iters=2, hyps=48, seed=7)
+
+
+def _ragged_pair():
+    W, H = 77, 53
+    rng = np.random.default_rng(31)
+    bg = synth.Layer(H=synth.similarity_about(38, 26, 1.02, 2.0, 3.0, -2.0))
+    fg = synth.Layer(H=synth.translation(-4, 3), poly=np.array([[20.0, 10], [50, 14], [46, 40], [18, 36]]))
+    return synth.render([bg, fg], W, H, rng)
+
+
+CASES = {
+    "tiny_c5": (lambda: synth.tiny_pair(0), TINY_PARAMS),
+    "tiny_c3": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, C=3, grad_weight=0.0)),
+    "ragged": (_ragged_pair, RAGGED),
+}
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("C", [3, 5])
+def test_features_bitexact(C, fp16):
+    msgpm = _need_gpu()
+    pair = _ragged_pair()
+    g = msgpm.Pair(77, 53, **_gpu_params(dict(C=C, fp16=fp16, blocks=(16,))))
+    g.set_features(pair.frame1, pair.frame2)
+    for f, frame in enumerate((pair.frame1, pair.frame2)):
+        ref = oracle.features(frame, C=C, fp16=fp16)
+        got = g.features(f)
+        assert np.array_equal(ref.view(np.uint32), got.view(np.uint32))
+
+
+def test_init_nnf_bitexact_and_given_nnf_clamped():
+    msgpm = _need_gpu()
+    pair = synth.tiny_pair(0)
+    o = oracle.Oracle(pair.frame1, pair.frame2, **TINY_PARAMS)
+    g = msgpm.Pair(128, 96, **_gpu_params(TINY_PARAMS))
+    g.set_features(pair.frame1, pair.frame2)
+    g.init_state()
+    for d in range(2):
+        o.nnf_init(d)
+        assert np.array_equal(g.nnf(d).cpu().numpy(), o.nnf[d])
+        assert (g.win(d).cpu().numpy() == -1).all() and (g.hlabel(d).cpu().numpy() == -1).all()
+    rng = np.random.default_rng(3)
+    given = [oracle.pack(rng.integers(-300, 300, 128 * 96), rng.integers(-300, 300, 128 * 96)) for _ in range(2)]
+    g.init_state(torch.from_numpy(given[0]), torch.from_numpy(given[1]))
+    for d in range(2):
+        o.set_nnf(d, given[d])
+        assert np.array_equal(g.nnf(d).cpu().numpy(), o.nnf[d])
+
+
+def _check_step(name, args, o, got, before, p, report):
+    r, C = p.get("r", 4), p.get("C", 5)
+    if name == "eval_cost":
+        for d in range(2):
+            tol = parity.cost_tol(o.cost[d], r, C)
+            fin = np.isfinite(o.cost[d])
+            assert np.array_equal(np.isfinite(got["cost"][d]), fin), (name, args, d)
+            err = np.abs(got["cost"][d][fin] - o.cost[d][fin])
+            assert (err <= tol[fin]).all(), (name, args, d, float(err.max()))
+    elif name == "pm_halfsweep":
+        for d in range(2):
+            flagged = (o.pflag[d] & (oracle.F_COST | oracle.F_ROUND)) != 0
+            diff = got["nnf"][d] != o.nnf[d]
+            report["pm_flagged"] += int(flagged.sum())
+            report["pm_flagged_diff"] += int((diff & flagged).sum())
+            report["pm_unexplained"] += int((diff & ~flagged).sum())
+            same = ~diff & np.isfinite(o.cost[d])
+            tol = parity.cost_tol(o.cost[d], r, C)
+            err = np.abs(got["cost"][d] - o.cost[d])
+            assert (err[same] <= tol[same]).all(), (name, args, d, float(err[same].max()))
+        assert report["pm_unexplained"] == 0, (name, args, report)
+    elif name == "ransac":
+        bad = parity.compare_planes(o, got["planes"])
+        if bad:
+            flagged = np.nonzero(o.bflag)[0]
+            bad_loose = parity.compare_planes(o, got["planes"], sel=~(o.bflag > 0), exact=True)
+            report["ransac_nonexact"] += 1
+            assert not bad_loose, (name, args, bad, "unflagged:", bad_loose, len(flagged))
+    elif name == "assign":
+        tent = args[2]
+        wk, lk = ("twin", "tloss") if tent else ("win", "loss")
+        for d in range(2):
+            ow = (o.twin if tent else o.win)[d]
+            ol = (o.tloss if tent else o.loss)[d]
+            assert np.array_equal(got[wk][d], ow), (name, args, d, int((got[wk][d] != ow).sum()))
+            assert np.array_equal(got[lk][d], ol), (name, args, d)
+    elif name == "symmetry":
+        bad = parity.compare_planes(o, got["planes"])
+        assert not bad, (name, args, bad)
+    elif name == "fb_unassign":
+        for d in range(2):
+            assert np.array_equal(got["win"][d], o.win[d]), (name, d)
+            assert np.array_equal(got["loss"][d], o.loss[d]), (name, d)
+    elif name == "nnf_update":
+        for d in range(2):
+            assert np.array_equal(got["nnf"][d], o.nnf[d]), (name, args, d)
+            assert np.array_equal(got["hlabel"][d], o.hlabel[d]), (name, args, d)
+
+
+def _gpu_step(g, name, args):
+    if name == "eval_cost":
+        g.eval_cost(*args)
+    else:
+        getattr(g, name)(*args)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_lockstep_pipeline(case):
+    """Every phase of the pipeline, GPU fed the oracle's state, outputs compared."""
+    msgpm = _need_gpu()
+    make, p = CASES[case]
+    pair = make()
+    H, W = pair.shape
+    o = oracle.Oracle(pair.frame1, pair.frame2, **p)
+    g = msgpm.Pair(W, H, **_gpu_params(p))
+    g.set_features(pair.frame1, pair.frame2)
+    for f in range(2):
+        assert np.array_equal(g.features(f).view(np.uint32), o.feat[f].view(np.uint32))
+    g.init_state()
+    for d in range(2):
+        o.nnf_init(d)
+    report = dict(pm_flagged=0, pm_flagged_diff=0, pm_unexplained=0, ransac_nonexact=0, steps=0)
+    for name, args in o.schedule():
+        for d in range(2):
+            o.pflag[d][:] = 0
+        o.bflag[:] = 0
+        parity.push_state(o, g)
+        before = None
+        o.run_step(name, args)
+        _gpu_step(g, name, args)
+        got = parity.pull_state(g)
+        _check_step(name, args, o, got, before, p, report)
+        report["steps"] += 1
+    # outputs
+    parity.push_state(o, g)
+    flows_g, occs_g = g.finalize()
+    for d in range(2):
+        fo, oo = o.finalize(d)
+        assert np.array_equal(occs_g[d].cpu().numpy(), oo)
+        assert np.array_equal(flows_g[d].cpu().numpy(), fo)
+        c = g.cost(d).cpu().numpy()
+        asg = o.win[d] >= 0
+        tol = parity.cost_tol(o.cost[d], p.get("r", 4), p.get("C", 5))
+        assert (np.abs(c - o.cost[d])[asg] <= tol[asg]).all()
+    print(case, report)
+
+
+@pytest.mark.parametrize("case", ["tiny_c5"])
+def test_solve_end_to_end(case):
+    """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
+    so the comparison is statistical: offsets, masks and flows of the GPU run
+    against the oracle run."""
+    msgpm = _need_gpu()
+    make, p = CASES[case]
+    pair = make()
+    H, W = pair.shape
+    o = oracle.Oracle(pair.frame1, pair.frame2, **p)
+    fo, oo = o.solve()
+    g = msgpm.Pair(W, H, **_gpu_params(p))
+    fg, og = g.solve(pair.frame1, pair.frame2)
+    torch.cuda.synchronize()
+    for d in range(2):
+        og_ = og[d].cpu().numpy()
+        fg_ = fg[d].cpu().numpy()
+        occ_agree = (og_ == oo[d]).mean()
+        both = (og_ == 0) & (oo[d] == 0)
+        epe_delta = np.linalg.norm(fg_ - fo[d], axis=-1)[both].mean()
+        nnf_agree = (g.nnf(d).cpu().numpy() == o.nnf[d]).mean()
+        print(case, d, "occ agree", occ_agree, "nnf agree", nnf_agree, "EPE delta", epe_delta)
+        assert occ_agree > 0.98
+        assert epe_delta <= 0.01
+
+
+def test_solve_is_deterministic():
+    msgpm = _need_gpu()
+    pair = synth.tiny_pair(0)
+    outs = []
+    for _ in range(2):
+        g = msgpm.Pair(128, 96, **_gpu_params(TINY_PARAMS))
+        fg, og = g.solve(pair.frame1, pair.frame2)
+        torch.cuda.synchronize()
+        outs.append((fg[0].cpu().numpy(), og[0].cpu().numpy(), g.planes()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2].view(np.uint8), outs[1][2].view(np.uint8))
+
+
+def test_invalid_arguments_raise():
+    msgpm = _need_gpu()
+    with pytest.raises(msgpm.MsgpmError):
+        msgpm.Pair(128, 96, r=7)
+    g = msgpm.Pair(64, 48, **_gpu_params(dict(blocks=(16,), r=2, C=3)))
+    with pytest.raises(msgpm.MsgpmError):
+        g.ransac(3, 1)
+    with pytest.raises(msgpm.MsgpmError):
+        g.pm_halfsweep(2, 0, 0, 0)
