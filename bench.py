@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput of the MSGPM hot path on one MI355X.
+
+One step = one whole pipeline run (libmsgpm msgpm_solve) over a frame pair
+already resident in HBM: features, random initial NNF, PatchMatch initial
+pass, three plane-fit levels (two RANSAC stages, assignment, plane symmetry,
+forward-backward check, NNF update, restricted PatchMatch pass) and the
+outputs (flow, occlusion mask, plane table) of both directions.
+
+Workload: a synthetic 1024x436 piecewise-planar pair (seed 0) standing in for
+the MPI-Sintel frames of the paper's experiments; 9x9 patches over RGB + luma
+gradients, windows 64/32/16, 8 PatchMatch iterations per pass, 256 RANSAC
+hypotheses per window, FP32 patch costs, FP64 plane fits.
+
+Prints one JSON line: flow Mpix/s, the dominant kernel's roofline (timed with
+HIP events around each launch inside the timed region) and the FP64 CPU oracle
+timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+W, H = 1024, 436
+PARAMS = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0, seed=0)
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
+
+
+def flops_per_eval(kind: str, r: int, C: int) -> int:
+    """Algorithmic FP32 flops of one patch-cost evaluation (FMA = 2).
+    Identity patch: per tap and channel a difference and a multiply-add (3),
+    gradient channels one more multiply for their weight.  Distorted patch:
+    each value is bilinear (3 lerps = 3 x (sub + FMA) = 9 flops) before that."""
+    taps = (2 * r + 1) ** 2
+    extra = 2 if C == 5 else 0
+    if kind == "identity":
+        return taps * (3 * C + extra)
+    return taps * (12 * C + extra)
+
+
+def cpu_baseline(seconds_hint: float = 25.0) -> dict:
+    """The FP64 oracle (single-threaded C) over the whole pipeline on a
+    128x56 instance of the same scene generator (lengths scaled by 1/8), same
+    method parameters and a first random-search radius of 1024 as in the full
+    workload."""
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from paper_1804_03787_amd import synth
+    sw, sh = 128, 56
+    pair = synth.planar_pair(sw, sh, seed=0, scale=0.125)
+    o = oracle.Oracle(pair.frame1, pair.frame2, R0=1024, **PARAMS)
+    t0 = time.perf_counter()
+    o.solve()
+    dt = time.perf_counter() - t0
+    return {"value": round(sw * sh / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole pipeline, both directions, on a {sw}x{sh} instance of the 1024x436 scene "
+                      f"generator (lengths x1/8), same parameters, R0=1024; {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not supported "
+              "(pairs are independent, so more GPUs would run more pairs; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1804_03787_amd import msgpm, synth
+
+    msgpm.lib()  # fails loudly if the HIP library is missing
+    pair = synth.planar_pair(W, H, seed=0)
+    f1 = torch.from_numpy(pair.frame1).cuda()
+    f2 = torch.from_numpy(pair.frame2).cuda()
+    params = dict(PARAMS, fp16=args.fp16)
+    g = msgpm.Pair(W, H, **params)
+    flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
+    occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    for _ in range(args.warmup):
+        g.solve(f1, f2, out=(flows, occs))
+    torch.cuda.synchronize()
+    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    msgpm.timing_enable(True)
+    msgpm.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.solve(f1, f2, out=(flows, occs))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = msgpm.timing_read()
+    msgpm.timing_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = W * H / (ms_per_step / 1e3) / 1e6
+    print(f"bench: timed {args.steps} steps, {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # evaluations of the last step (every step is identical: same inputs and seed)
+    cnt = g.counters()
+    ev_init = sum(cnt["pm_init"])
+    ev_restr = sum(cnt["pm_restricted"])
+    occ0 = occs[0].float().mean().item()
+    kernel_ms = {k: v[0] / args.steps for k, v in timing.items()}
+    launches = {k: v[1] / args.steps for k, v in timing.items()}
+    dominant = max(kernel_ms, key=kernel_ms.get)
+    r, C = params["r"], params["C"]
+    work = {"pm_init": ev_init * flops_per_eval("identity", r, C),
+            "pm_restricted": ev_restr * flops_per_eval("warped", r, C)}
+    roofline = None
+    if dominant in work and kernel_ms[dominant] > 0:
+        achieved = work[dominant] / (kernel_ms[dominant] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                    "kernel": "k_pm_halfsweep (" + ("identity" if dominant == "pm_init" else "warped") + " patches)",
+                    "avg_launch_us": round(kernel_ms[dominant] * 1e3 / max(launches[dominant], 1), 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "flow Mpix/s (full pipeline)",
+        "value": round(value, 4),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if not args.fp16 else "f16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
+                               "8 PM iterations, 256 RANSAC hypotheses",
+                   "width": W, "height": H, "seed": 0, "fp16_storage": bool(args.fp16)},
+        "warped_patch_evals_per_s": round((ev_init + ev_restr) / (ms_per_step * 1e-3), 1),
+        "evals_per_step": {"pm_init": ev_init, "pm_restricted": ev_restr, "eval_cost": sum(cnt["eval_cost"])},
+        "kernel_ms_per_step": {k: round(v, 3) for k, v in kernel_ms.items()},
+        "occluded_fraction_dir0": round(occ0, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -104,7 +104,7 @@ typedef struct msgpm_layout {
   uint64_t twin[2];        /* int32: tentative assignment (scratch) */
   uint64_t tloss[2];       /* double: its loss (scratch) */
   uint64_t planes;         /* msgpm_plane[n_planes] */
-  uint64_t counters;       /* uint64[8]: [0], [1] warped-patch evaluations per direction */
+  uint64_t counters;       /* uint64[8]: evaluation counters, see msgpm_timing_read */
   int32_t n_planes;
   int32_t n_levels;
   int32_t level_blocks[MSGPM_MAX_LEVELS]; /* windows per level and stage */
@@ -196,6 +196,37 @@ msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void
    mask of both directions (see msgpm_solve). */
 msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
                             uint8_t* d_occ1, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing.  While enabled, the library records a pair of HIP events on
+ * the launch stream around every kernel it launches (from any entry point) and
+ * attributes the elapsed time to one of the kinds below.  msgpm_timing_read
+ * waits for the recorded events, writes the total milliseconds and launch count
+ * per kind since the last read (arrays of MSGPM_TIMER_KINDS elements, either
+ * may be NULL) and starts a new accumulation.  Event objects are created on
+ * first use and reused; no device memory is allocated.
+ * ------------------------------------------------------------------------- */
+enum {
+  MSGPM_T_FEATURES = 0,
+  MSGPM_T_INIT = 1,
+  MSGPM_T_EVAL_COST = 2,
+  MSGPM_T_PM_INIT = 3,       /* PatchMatch half-sweeps of the initial pass (identity patches) */
+  MSGPM_T_PM_RESTRICTED = 4, /* PatchMatch half-sweeps restricted to unassigned pixels (warped patches) */
+  MSGPM_T_RANSAC = 5,
+  MSGPM_T_ASSIGN = 6,
+  MSGPM_T_SYMMETRY = 7,
+  MSGPM_T_FB = 8,
+  MSGPM_T_NNF_UPDATE = 9,
+  MSGPM_T_FINALIZE = 10,
+  MSGPM_TIMER_KINDS = 11
+};
+msgpm_status msgpm_timing_enable(int on);
+msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
+
+/* Counters in the workspace (uint64 at layout.counters): warped-patch
+   evaluations performed, per direction d = 0, 1:
+     [0 + d] initial PatchMatch pass, [2 + d] cost refreshes,
+     [4 + d] restricted PatchMatch passes.  Reset by msgpm_init_state. */
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -44,6 +46,39 @@ int block_count(int n, int B) {
 }
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+// Optional per-kind kernel timing with reusable HIP events.
+struct Timer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // events created so far, reused after each read
+  size_t used = 0;
+  std::vector<int> kinds;        // kind of each recorded (start, stop) pair
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Timer g_timer;
+
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& launch) {
+  if (!g_timer.on) return launch();
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  hipEvent_t a = g_timer.get(), b = g_timer.get();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e == hipSuccess) g_timer.kinds.push_back(kind);
+  return e;
+}
 
 // Validates *p and derives the kernel parameters and the workspace layout.
 msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
@@ -185,7 +220,7 @@ msgpm_status check_level(const Ctx& c, int level, int stage) {
 msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
   for (int it = 0; it < c.P.iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      msgpm_status st = check(launch_pm_halfsweep(c.P, c.w, colour, it, slot, restricted, c.s), "pm_halfsweep");
+      msgpm_status st = check(timed(restricted ? MSGPM_T_PM_RESTRICTED : MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, restricted, c.s); }), "pm_halfsweep");
       if (st != MSGPM_OK) return st;
     }
   return MSGPM_OK;
@@ -208,9 +243,9 @@ msgpm_status msgpm_features(const msgpm_params* p, const float* d_rgb1, const fl
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
-  st = check(launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s), "features");
+  st = check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s); }), "features");
   if (st != MSGPM_OK) return st;
-  return check(launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s), "features");
+  return check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s); }), "features");
 }
 
 msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
@@ -218,7 +253,7 @@ msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0,
   Ctx c;
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
-  return check(launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s), "init_state");
+  return check(timed(MSGPM_T_INIT, c.s, [&] { return launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s); }), "init_state");
 }
 
 msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* stream) {
@@ -226,7 +261,7 @@ msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* 
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if (mode < 0 || mode > 2) return fail(MSGPM_E_INVALID, "mode must be 0, 1 or 2");
-  return check(launch_eval_cost(c.P, c.w, mode, c.s), "eval_cost");
+  return check(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, mode, c.s); }), "eval_cost");
 }
 
 msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, int iter, int slot, int restricted,
@@ -236,7 +271,7 @@ msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, i
   if (st != MSGPM_OK) return st;
   if (colour != 0 && colour != 1) return fail(MSGPM_E_INVALID, "colour must be 0 or 1");
   if (iter < 0 || slot < 0 || slot > 255) return fail(MSGPM_E_INVALID, "iter or slot out of range");
-  return check(launch_pm_halfsweep(c.P, c.w, colour, iter, slot, restricted ? 1 : 0, c.s), "pm_halfsweep");
+  return check(timed(restricted ? MSGPM_T_PM_RESTRICTED : MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, iter, slot, restricted ? 1 : 0, c.s); }), "pm_halfsweep");
 }
 
 msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {
@@ -244,7 +279,7 @@ msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stag
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
-  return check(launch_ransac(c.P, c.w, level, stage, c.s), "ransac");
+  return check(timed(MSGPM_T_RANSAC, c.s, [&] { return launch_ransac(c.P, c.w, level, stage, c.s); }), "ransac");
 }
 
 msgpm_status msgpm_assign(const msgpm_params* p, void* d_ws, int level, int stage, int tentative, void* stream) {
@@ -252,7 +287,7 @@ msgpm_status msgpm_assign(const msgpm_params* p, void* d_ws, int level, int stag
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
-  return check(launch_assign(c.P, c.w, level, stage, tentative ? 1 : 0, c.s), "assign");
+  return check(timed(MSGPM_T_ASSIGN, c.s, [&] { return launch_assign(c.P, c.w, level, stage, tentative ? 1 : 0, c.s); }), "assign");
 }
 
 msgpm_status msgpm_symmetry(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {
@@ -260,14 +295,14 @@ msgpm_status msgpm_symmetry(const msgpm_params* p, void* d_ws, int level, int st
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if ((st = check_level(c, level, stage)) != MSGPM_OK) return st;
-  return check(launch_symmetry(c.P, c.w, level, stage, c.s), "symmetry");
+  return check(timed(MSGPM_T_SYMMETRY, c.s, [&] { return launch_symmetry(c.P, c.w, level, stage, c.s); }), "symmetry");
 }
 
 msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream) {
   Ctx c;
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
-  return check(launch_fb_unassign(c.P, c.w, c.s), "fb_unassign");
+  return check(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
 }
 
 msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void* stream) {
@@ -275,7 +310,7 @@ msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if ((st = check_level(c, level, 1)) != MSGPM_OK) return st;
-  return check(launch_nnf_update(c.P, c.w, level, c.s), "nnf_update");
+  return check(timed(MSGPM_T_NNF_UPDATE, c.s, [&] { return launch_nnf_update(c.P, c.w, level, c.s); }), "nnf_update");
 }
 
 msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
@@ -283,9 +318,9 @@ msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, f
   Ctx c;
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
-  st = check(launch_eval_cost(c.P, c.w, 2, c.s), "eval_cost");
+  st = check(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 2, c.s); }), "eval_cost");
   if (st != MSGPM_OK) return st;
-  return check(launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s), "finalize");
+  return check(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 }
 
 msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
@@ -300,26 +335,58 @@ msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float
     msgpm_status s_ = check((expr), what);       \
     if (s_ != MSGPM_OK) return s_;               \
   } while (0)
-  RUN(launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s), "features");
-  RUN(launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s), "features");
-  RUN(launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s), "init_state");
-  RUN(launch_eval_cost(c.P, c.w, 0, c.s), "eval_cost");
+  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s); }), "features");
+  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s); }), "features");
+  RUN(timed(MSGPM_T_INIT, c.s, [&] { return launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s); }), "init_state");
+  RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 0, c.s); }), "eval_cost");
   if ((st = run_pm_pass(c, 0, 0)) != MSGPM_OK) return st;
   for (int l = 0; l < c.P.n_levels; ++l) {
     for (int stage = 1; stage <= 2; ++stage) {
-      RUN(launch_ransac(c.P, c.w, l, stage, c.s), "ransac");
-      RUN(launch_assign(c.P, c.w, l, stage, 1, c.s), "assign");
-      RUN(launch_symmetry(c.P, c.w, l, stage, c.s), "symmetry");
-      RUN(launch_assign(c.P, c.w, l, stage, 0, c.s), "assign");
+      RUN(timed(MSGPM_T_RANSAC, c.s, [&] { return launch_ransac(c.P, c.w, l, stage, c.s); }), "ransac");
+      RUN(timed(MSGPM_T_ASSIGN, c.s, [&] { return launch_assign(c.P, c.w, l, stage, 1, c.s); }), "assign");
+      RUN(timed(MSGPM_T_SYMMETRY, c.s, [&] { return launch_symmetry(c.P, c.w, l, stage, c.s); }), "symmetry");
+      RUN(timed(MSGPM_T_ASSIGN, c.s, [&] { return launch_assign(c.P, c.w, l, stage, 0, c.s); }), "assign");
     }
-    RUN(launch_fb_unassign(c.P, c.w, c.s), "fb_unassign");
-    RUN(launch_nnf_update(c.P, c.w, l, c.s), "nnf_update");
-    RUN(launch_eval_cost(c.P, c.w, 1, c.s), "eval_cost");
+    RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
+    RUN(timed(MSGPM_T_NNF_UPDATE, c.s, [&] { return launch_nnf_update(c.P, c.w, l, c.s); }), "nnf_update");
+    RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 1, c.s); }), "eval_cost");
     if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
   }
-  RUN(launch_eval_cost(c.P, c.w, 2, c.s), "eval_cost");
-  RUN(launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s), "finalize");
+  RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 2, c.s); }), "eval_cost");
+  RUN(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 #undef RUN
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  g_timer.on = on != 0;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_timing_read(double* ms, int64_t* launches) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  double t[MSGPM_TIMER_KINDS] = {0};
+  int64_t n[MSGPM_TIMER_KINDS] = {0};
+  for (size_t i = 0; i < g_timer.kinds.size(); ++i) {
+    hipEvent_t a = g_timer.pool[2 * i], b = g_timer.pool[2 * i + 1];
+    hipError_t e = hipEventSynchronize(b);
+    float dt = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&dt, a, b);
+    if (e != hipSuccess) {
+      g_timer.kinds.clear();
+      g_timer.used = 0;
+      return check(e, "timing_read");
+    }
+    t[g_timer.kinds[i]] += dt;
+    n[g_timer.kinds[i]] += 1;
+  }
+  g_timer.kinds.clear();
+  g_timer.used = 0;
+  for (int k = 0; k < MSGPM_TIMER_KINDS; ++k) {
+    if (ms) ms[k] = t[k];
+    if (launches) launches[k] = n[k];
+  }
   return MSGPM_OK;
 }
 

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
       evals = 1;
     }
   }
-  count_evals(&w.counters[dir], evals);
+  count_evals(&w.counters[2 + dir], evals);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
     }
     if (j != 0) evals = 0;
   }
-  count_evals(&w.counters[dir], evals);
+  count_evals(&w.counters[(restricted ? 4 : 0) + dir], evals);
 }
 
 // ---------------------------------------------------------------------------

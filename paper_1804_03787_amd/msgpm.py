@@ -85,6 +85,10 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.msgpm_timing_enable.argtypes = [ctypes.c_int]
+        L.msgpm_timing_enable.restype = ctypes.c_int
+        L.msgpm_timing_read.argtypes = [vp, vp]
+        L.msgpm_timing_read.restype = ctypes.c_int
         L.msgpm_last_error.restype = ctypes.c_char_p
         L.msgpm_last_error.argtypes = []
         _lib = L
@@ -95,6 +99,22 @@ def _call(name, *args):
     st = getattr(lib(), name)(*args)
     if st != 0:
         raise MsgpmError(name, st, lib().msgpm_last_error().decode())
+
+
+TIMER_KINDS = ["features", "init", "eval_cost", "pm_init", "pm_restricted", "ransac", "assign", "symmetry", "fb",
+               "nnf_update", "finalize"]
+
+
+def timing_enable(on: bool = True):
+    _call("msgpm_timing_enable", int(on))
+
+
+def timing_read() -> dict:
+    """Milliseconds and launch counts per kernel kind since the last read."""
+    ms = np.zeros(len(TIMER_KINDS), np.float64)
+    n = np.zeros(len(TIMER_KINDS), np.int64)
+    _call("msgpm_timing_read", ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMER_KINDS)}
 
 
 def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 32, 16), iters: int = 8,
@@ -180,8 +200,10 @@ class Pair:
         assert arr.dtype == PLANE_DTYPE and len(arr) == self.n_planes
         self.planes_bytes().copy_(torch.from_numpy(arr.view(np.uint8).copy()).to(self.device))
 
-    def counters(self) -> np.ndarray:
-        return self._view(self.L.counters, 8, torch.int64).cpu().numpy().astype(np.uint64)
+    def counters(self) -> dict:
+        """Warped-patch evaluations of the last pipeline run, per direction."""
+        c = self._view(self.L.counters, 8, torch.int64).cpu().numpy()
+        return {"pm_init": c[0:2].tolist(), "eval_cost": c[2:4].tolist(), "pm_restricted": c[4:6].tolist()}
 
     def features(self, f) -> np.ndarray:
         """Features of frame f as (H, W, C) float32 on the host."""

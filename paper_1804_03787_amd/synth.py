@@ -169,14 +169,14 @@ def _top_layer_frame2(layers, xs, ys):
     return top, pre
 
 
-def ground_truth(layers, W, H, top1=None):
-    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+def ground_truth(layers, W, H, top1=None, return_cover=False, step=1):
+    ys, xs = np.mgrid[0:H:step, 0:W:step].astype(np.float64)
     if top1 is None:
         top1 = _top_layer_frame1(layers, xs, ys)
-    flow = np.zeros((H, W, 2))
-    occ = np.zeros((H, W), dtype=np.uint8)
-    qx = np.zeros((H, W))
-    qy = np.zeros((H, W))
+    flow = np.zeros(xs.shape + (2,))
+    occ = np.zeros(xs.shape, dtype=np.uint8)
+    qx = np.zeros(xs.shape)
+    qy = np.zeros(xs.shape)
     for i, L in enumerate(layers):
         m = top1 == i
         if not m.any():
@@ -188,13 +188,15 @@ def ground_truth(layers, W, H, top1=None):
     flow[..., 1] = qy - ys
     out = (qx < 0) | (qx > W - 1) | (qy < 0) | (qy > H - 1)
     # a pixel is visible in frame 2 only if its own layer is the top one at its target
-    top_at_q = np.full((H, W), -1, dtype=np.int32)
+    top_at_q = np.full(xs.shape, -1, dtype=np.int32)
     for i in range(len(layers) - 1, -1, -1):
         L = layers[i]
         px, py, w = _apply(np.linalg.inv(L.H), qx, qy)
         m = (top_at_q < 0) & (w > 0) & L.inside(px, py)
         top_at_q[m] = i
     occ[(top_at_q != top1) | out] = 1
+    if return_cover:
+        return flow.astype(np.float32), occ, top1, top_at_q, out
     return flow.astype(np.float32), occ
 
 
@@ -236,28 +238,51 @@ def _random_motion(rng, cx, cy, tmax, persp=2e-5):
                             rng.uniform(-persp, persp), rng.uniform(-persp, persp))
 
 
-def planar_pair(W: int = 1024, H: int = 436, seed: int = 0, n_quads: int = 20, tmax: float = 100.0,
-                occ_band: tuple = (0.045, 0.055), gain_range: tuple = (0.8, 1.2), max_fg: int = 40) -> Pair:
-    """Piecewise-planar scene shaped like the paper's 1024x436 frames: a
-    perspective background, n_quads convex quads with their own homographies in
-    random z-order, foreground quads added until the ground-truth occlusion
-    fraction falls in occ_band, and a global brightness gain on frame 2."""
+def planar_pair(W: int = 1024, H: int = 436, seed: int = 0, n_quads: int = 20, cam_t: float = 30.0,
+                rel_t: float = 12.0, fg_t: float = 40.0, fg_occ: tuple = (0.045, 0.055),
+                gain_range: tuple = (0.8, 1.2), max_tries: int = 400, scale: float = 1.0) -> Pair:
+    """Piecewise-planar scene shaped like the paper's 1024x436 frames.
+
+    * camera: a perspective similarity of the whole frame about its centre
+      (translation up to cam_t px, scale 0.95-1.05, rotation up to 5 degrees,
+      perspective terms up to 2e-5) applied to the background;
+    * n_quads convex quads (radius 40-160 px) in random z-order, each moving
+      with the camera composed with its own similarity about its centroid
+      (translation up to rel_t px, scale 0.97-1.03, rotation up to 3 degrees):
+      absolute displacements reach about 100 px at the frame border;
+    * foreground quads (radius 20-80 px, own translation up to fg_t px) on
+      top, added until the share of pixels hidden in frame 2 by a foreground
+      quad lies in fg_occ;
+    * frame 2 multiplied by a global gain drawn from gain_range.
+    scale multiplies every length (radii, translations) for smaller instances.
+    """
+    cam_t, rel_t, fg_t = cam_t * scale, rel_t * scale, fg_t * scale
     rng = np.random.default_rng(seed)
-    layers = [Layer(H=_random_motion(rng, W / 2, H / 2, tmax))]
+    cam = similarity_about(W / 2, H / 2, rng.uniform(0.95, 1.05), rng.uniform(-5, 5), rng.uniform(-cam_t, cam_t),
+                           rng.uniform(-cam_t, cam_t), rng.uniform(-2e-5, 2e-5), rng.uniform(-2e-5, 2e-5))
+    layers = [Layer(H=cam)]
     for _ in range(n_quads):
-        q = _random_convex_quad(rng, W, H, 40, 160)
+        q = _random_convex_quad(rng, W, H, 40 * scale, 160 * scale)
         c = q.mean(axis=0)
-        layers.append(Layer(H=_random_motion(rng, c[0], c[1], tmax), poly=q))
-    # z-order is the draw order, which is already random
-    lo, hi = occ_band
-    frac = ground_truth(layers, W, H)[1].mean()
+        rel = similarity_about(c[0], c[1], rng.uniform(0.97, 1.03), rng.uniform(-3, 3), rng.uniform(-rel_t, rel_t),
+                               rng.uniform(-rel_t, rel_t))
+        layers.append(Layer(H=cam @ rel, poly=q))
+    n_base = len(layers)
+    lo, hi = fg_occ
+
+    def hidden_by_fg(ls):  # on every second pixel in x and y
+        _, _, top1, top_q, out = ground_truth(ls, W, H, return_cover=True, step=2)
+        return float(((top1 < n_base) & (top_q >= n_base) & ~out).mean())
+
+    frac = 0.0
     tries = 0
-    while frac < lo and tries < max_fg * 10:
+    while frac < lo and tries < max_tries:
         tries += 1
-        q = _random_convex_quad(rng, W, H, 20, 80)
+        q = _random_convex_quad(rng, W, H, 20 * scale, 80 * scale)
         c = q.mean(axis=0)
-        cand = Layer(H=_random_motion(rng, c[0], c[1], 1.2 * tmax), poly=q)
-        f = ground_truth(layers + [cand], W, H)[1].mean()
+        rel = similarity_about(c[0], c[1], 1.0, rng.uniform(-3, 3), rng.uniform(-fg_t, fg_t), rng.uniform(-fg_t, fg_t))
+        cand = Layer(H=cam @ rel, poly=q)
+        f = hidden_by_fg(layers + [cand])
         if f <= hi:
             layers.append(cand)
             frac = f
