@@ -110,17 +110,21 @@ def main() -> int:
     value = W * H / (ms_per_step / 1e3) / 1e6
     print(f"bench: timed {args.steps} steps, {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # evaluations of the last step (every step is identical: same inputs and seed)
+    # evaluations of the last step (every step is identical: same inputs and seed);
+    # a candidate rejected early by its partial sum counts for the rows it computed
     cnt = g.counters()
+    taps_rows = 2 * PARAMS["r"] + 1
     ev_init = sum(cnt["pm_init"])
     ev_restr = sum(cnt["pm_restricted"])
+    full_init = sum(cnt["pm_init_rows"]) / taps_rows
+    full_restr = sum(cnt["pm_restricted_rows"]) / taps_rows
     occ0 = occs[0].float().mean().item()
     kernel_ms = {k: v[0] / args.steps for k, v in timing.items()}
     launches = {k: v[1] / args.steps for k, v in timing.items()}
     dominant = max(kernel_ms, key=kernel_ms.get)
     r, C = params["r"], params["C"]
-    work = {"pm_init": ev_init * flops_per_eval("identity", r, C),
-            "pm_restricted": ev_restr * flops_per_eval("warped", r, C)}
+    work = {"pm_init": full_init * flops_per_eval("identity", r, C),
+            "pm_restricted": full_restr * flops_per_eval("warped", r, C)}
     roofline = None
     if dominant in work and kernel_ms[dominant] > 0:
         achieved = work[dominant] / (kernel_ms[dominant] * 1e-3) / 1e12
@@ -151,7 +155,8 @@ def main() -> int:
                                "8 PM iterations, 256 RANSAC hypotheses",
                    "width": W, "height": H, "seed": 0, "fp16_storage": bool(args.fp16)},
         "warped_patch_evals_per_s": round((ev_init + ev_restr) / (ms_per_step * 1e-3), 1),
-        "evals_per_step": {"pm_init": ev_init, "pm_restricted": ev_restr, "eval_cost": sum(cnt["eval_cost"])},
+        "evals_per_step": {"pm_init": ev_init, "pm_restricted": ev_restr, "eval_cost": sum(cnt["eval_cost"]),
+                           "pm_init_full_equiv": round(full_init), "pm_restricted_full_equiv": round(full_restr)},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in kernel_ms.items()},
         "occluded_fraction_dir0": round(occ0, 4),
         "roofline": roofline,

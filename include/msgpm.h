@@ -104,15 +104,15 @@ typedef struct msgpm_layout {
   uint64_t twin[2];        /* int32: tentative assignment (scratch) */
   uint64_t tloss[2];       /* double: its loss (scratch) */
   uint64_t planes;         /* msgpm_plane[n_planes] */
-  uint64_t counters;       /* uint64[8]: evaluation counters, see msgpm_timing_read */
+  uint64_t counters;       /* uint64[16][64]: evaluation counters, see below */
   int32_t n_planes;
   int32_t n_levels;
   int32_t level_blocks[MSGPM_MAX_LEVELS]; /* windows per level and stage */
   int32_t level_nbx[MSGPM_MAX_LEVELS];    /* windows per row */
 } msgpm_layout;
-/* Feature storage of one frame (FP32): width*height float4 (R, G, B, gx or 0)
-   followed, when channels = 5, by width*height float (gy).  FP16: width*height
-   records of 8 halves (R, G, B, gx, gy, 0, 0, 0). */
+/* Feature storage of one frame: width*height + 1 pixel records, interleaved,
+   the last one zero.  FP32: `channels` floats (R, G, B[, gx, gy]).  FP16:
+   4 halves (R, G, B, 0) for 3 channels, 6 halves (R, G, B, gx, gy, 0) for 5. */
 
 /* Fills *out for the given parameters; validates them.  No device work. */
 msgpm_status msgpm_layout_query(const msgpm_params* p, msgpm_layout* out);
@@ -223,10 +223,14 @@ enum {
 msgpm_status msgpm_timing_enable(int on);
 msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
 
-/* Counters in the workspace (uint64 at layout.counters): warped-patch
-   evaluations performed, per direction d = 0, 1:
-     [0 + d] initial PatchMatch pass, [2 + d] cost refreshes,
-     [4 + d] restricted PatchMatch passes.  Reset by msgpm_init_state. */
+/* Counters in the workspace (uint64[16][64] at layout.counters: 16 counters,
+   each kept as 64 partial sums to be added by the reader), per direction
+   d = 0, 1, reset by msgpm_init_state:
+     [0 + d] candidates evaluated by the initial PatchMatch pass,
+     [2 + d] cost refreshes, [4 + d] candidates of the restricted passes,
+     [6 + d], [8 + d] patch rows (2r+1 taps each) actually computed by the
+     initial and restricted passes (a candidate rejected early by its partial
+     sum computes fewer rows). */
 
 #ifdef __cplusplus
 }

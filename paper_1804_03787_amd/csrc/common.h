@@ -12,6 +12,8 @@ namespace msgpm {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kCounterKinds = 16;
+constexpr int kCounterStripes = 64;  // copies of every counter, summed by the reader
 
 // Parameters as kernels see them (passed by value).
 struct DevParams {

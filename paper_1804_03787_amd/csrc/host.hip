@@ -139,7 +139,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     memset(&o, 0, sizeof o);
     const uint64_t n = (uint64_t)d.W * d.H;
     uint64_t cur = 0;
-    o.feat_bytes = d.fp16 ? n * 16 : n * 16 + (d.C == 5 ? n * 4 : 0);
+    o.feat_bytes = (n + 1) * (d.fp16 ? (d.C == 3 ? 8 : 12) : 4 * (uint64_t)d.C);
     for (int f = 0; f < 2; ++f) {
       o.feat[f] = cur;
       cur = align256(cur + o.feat_bytes);
@@ -164,7 +164,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     o.n_planes = 2 * d.planes_per_dir;
     cur = align256(cur + (uint64_t)o.n_planes * sizeof(msgpm_plane));
     o.counters = cur;
-    cur = align256(cur + 8 * sizeof(uint64_t));
+    cur = align256(cur + (uint64_t)kCounterKinds * kCounterStripes * sizeof(uint64_t));
     o.total_bytes = cur;
     o.n_levels = d.n_levels;
     for (int l = 0; l < d.n_levels; ++l) {

@@ -3,8 +3,10 @@
 // Features: the patch cost of the paper compares colours (Sec. 3.1.3); the cost
 // here may add luma gradients.  Luma Y = (0.299 R + 0.587 G) + 0.114 B in FP32
 // without contraction; gx = 0.5 (Y(x+1) - Y(x-1)), gy likewise, with replicate
-// borders.  Stored per pixel as float4 (R, G, B, gx) plus a float plane (gy), or
-// as 8 halves (R, G, B, gx, gy, 0, 0, 0) in the FP16 form.
+// borders.  Stored interleaved per pixel: C floats (R, G, B[, gx, gy]), or in
+// the FP16 form 4 halves (R, G, B, 0) / 6 halves (R, G, B, gx, gy, 0).  One zero
+// pixel follows the last one so that a horizontal pair load at the last pixel
+// stays inside the buffer.
 #include "common.h"
 
 #include <hip/hip_fp16.h>
@@ -23,28 +25,33 @@ __device__ inline float luma(const float* rgb, int p) {
 __global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ rgb, int W, int H, int C, int fp16,
                                                     void* __restrict__ feat) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
-  if (p >= W * H) return;
-  const int x = p % W, y = p / W;
-  const float R = rgb[3 * p], G = rgb[3 * p + 1], B = rgb[3 * p + 2];
-  float gx = 0.f, gy = 0.f;
-  if (C == 5) {
-    const int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
-    const int yu = y > 0 ? y - 1 : 0, yd = y < H - 1 ? y + 1 : H - 1;
-    gx = 0.5f * (luma(rgb, y * W + xr) - luma(rgb, y * W + xl));
-    gy = 0.5f * (luma(rgb, yd * W + x) - luma(rgb, yu * W + x));
+  const int n = W * H;
+  if (p > n) return;
+  float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (p < n) {
+    const int x = p % W, y = p / W;
+    v[0] = rgb[3 * p];
+    v[1] = rgb[3 * p + 1];
+    v[2] = rgb[3 * p + 2];
+    if (C == 5) {
+      const int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
+      const int yu = y > 0 ? y - 1 : 0, yd = y < H - 1 ? y + 1 : H - 1;
+      v[3] = 0.5f * (luma(rgb, y * W + xr) - luma(rgb, y * W + xl));
+      v[4] = 0.5f * (luma(rgb, yd * W + x) - luma(rgb, yu * W + x));
+    }
   }
   if (fp16) {
-    __half h[8] = {__float2half_rn(R), __float2half_rn(G), __float2half_rn(B), __float2half_rn(gx),
-                   __float2half_rn(gy), __float2half_rn(0.f), __float2half_rn(0.f), __float2half_rn(0.f)};
-    reinterpret_cast<uint4*>(feat)[p] = *reinterpret_cast<const uint4*>(h);
+    const int S = C == 3 ? 4 : 6;
+    __half* h = reinterpret_cast<__half*>(feat) + (size_t)S * p;
+    for (int k = 0; k < S; ++k) h[k] = __float2half_rn(k < C ? v[k] : 0.f);
   } else {
-    reinterpret_cast<float4*>(feat)[p] = make_float4(R, G, B, gx);
-    if (C == 5) reinterpret_cast<float*>(reinterpret_cast<float4*>(feat) + (size_t)W * H)[p] = gy;
+    float* f = reinterpret_cast<float*>(feat) + (size_t)C * p;
+    for (int k = 0; k < C; ++k) f[k] = v[k];
   }
 }
 
 hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s) {
-  const int n = P.W * P.H;
+  const int n = P.W * P.H + 1;  // pixels plus the zero pad pixel
   hipLaunchKernelGGL(k_features, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rgb, P.W, P.H, P.C, P.fp16,
                      feat);
   return hipGetLastError();
@@ -82,7 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const
 
 __global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) {
   const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k < 8 && blockIdx.x == 0) w.counters[k] = 0;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < kCounterKinds * kCounterStripes; c += gridDim.x * kBlock)
+    w.counters[c] = 0;
   if (k >= 2 * P.planes_per_dir) return;
   const int dir = k / P.planes_per_dir;
   int r = k - dir * P.planes_per_dir;
@@ -117,7 +125,7 @@ hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* ini
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int np = 2 * P.planes_per_dir;
-  const int nblk = (np > 8 ? np : 8);
+  const int nblk = np > kBlock ? np : kBlock;
   hipLaunchKernelGGL(k_init_planes, dim3((nblk + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P, w);
   return hipGetLastError();
 }

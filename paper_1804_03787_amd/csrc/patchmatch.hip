@@ -10,11 +10,15 @@
 //
 // Work mapping (gfx950, wave64): a pixel is handled by 2r+1 adjacent lanes, lane
 // j owning patch column dx = j - r for every candidate.  Each lane keeps its
-// column's source features and tap geometry in registers; a candidate costs
-// each lane 2r+1 gathers (4 bilinear corners in the distorted form, 1 for the
-// identity form) and the column partial sums are combined across the group in a
-// fixed order, so every lane of the group takes the same decisions.  Costs are
-// accumulated in FP32.
+// column's source features and tap geometry in registers.  A distorted tap
+// needs the horizontal corner pairs of two rows, each fetched as one
+// contiguous load (features are stored interleaved per pixel); integral
+// geometries (identity, integer translations) fetch one pixel per tap.  Column
+// partials are combined across the group in a fixed order, so every lane of the
+// group takes the same decisions.  Identity-patch candidates are evaluated in
+// batches whose gathers are in flight together; distorted-patch candidates one
+// at a time with an exact early rejection on partial sums (both schedules take
+// the decisions of a one-at-a-time loop).  Costs are accumulated in FP32.
 //
 // PatchMatch (propagation + random search, as used by the paper for its NNF,
 // Sec. 3.1) runs as red-black Jacobi half-sweeps: a pixel reads only the other
@@ -27,52 +31,94 @@
 
 namespace msgpm {
 
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f3u __attribute__((ext_vector_type(3), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u3u __attribute__((ext_vector_type(3), aligned(4)));
+typedef uint32_t u2u __attribute__((ext_vector_type(2), aligned(4)));
+
+__device__ inline float2 h2f(uint32_t u) { return __half22float2(__builtin_bit_cast(__half2, u)); }
+
+// Feature access.  FP32: C floats per pixel; FP16: C=3 -> 4 halves, C=5 -> 6
+// halves per pixel.  load1 reads pixel idx, load2 pixels idx and idx + 1 with
+// one contiguous access (the buffer is padded so idx + 1 always exists).
 template <int C, bool FP16>
-__device__ inline void load_px(const void* __restrict__ F, int npix, int idx, float* v) {
-  if constexpr (FP16) {
-    const uint4 u = reinterpret_cast<const uint4*>(F)[idx];
-    const float2 a = __half22float2(__builtin_bit_cast(__half2, u.x));
-    const float2 b = __half22float2(__builtin_bit_cast(__half2, u.y));
-    v[0] = a.x;
-    v[1] = a.y;
-    v[2] = b.x;
-    if constexpr (C == 5) {
-      const float2 c = __half22float2(__builtin_bit_cast(__half2, u.z));
-      v[3] = b.y;
-      v[4] = c.x;
-    }
-  } else {
-    const float4 a = reinterpret_cast<const float4*>(F)[idx];
-    v[0] = a.x;
-    v[1] = a.y;
-    v[2] = a.z;
-    if constexpr (C == 5) {
-      v[3] = a.w;
-      v[4] = reinterpret_cast<const float*>(reinterpret_cast<const float4*>(F) + npix)[idx];
+struct Px {
+  static __device__ inline void load1(const void* __restrict__ F, int idx, float* v) {
+    if constexpr (!FP16) {
+      const float* p = reinterpret_cast<const float*>(F) + (size_t)C * idx;
+      if constexpr (C == 3) {
+        const f3u a = *reinterpret_cast<const f3u*>(p);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z;
+      } else {
+        const f4u a = *reinterpret_cast<const f4u*>(p);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = p[4];
+      }
+    } else {
+      if constexpr (C == 3) {
+        const u2u u = *reinterpret_cast<const u2u*>(reinterpret_cast<const uint16_t*>(F) + 4 * (size_t)idx);
+        const float2 a = h2f(u.x), b = h2f(u.y);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x;
+      } else {
+        const u3u u = *reinterpret_cast<const u3u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx);
+        const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x;
+      }
     }
   }
-}
+  static __device__ inline void load2(const void* __restrict__ F, int idx, float* v, float* w) {
+    if constexpr (!FP16) {
+      const float* p = reinterpret_cast<const float*>(F) + (size_t)C * idx;
+      if constexpr (C == 3) {
+        const f4u a = *reinterpret_cast<const f4u*>(p);
+        const f2u b = *reinterpret_cast<const f2u*>(p + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; w[0] = a.w; w[1] = b.x; w[2] = b.y;
+      } else {
+        const f4u a = *reinterpret_cast<const f4u*>(p);
+        const f4u b = *reinterpret_cast<const f4u*>(p + 4);
+        const f2u c = *reinterpret_cast<const f2u*>(p + 8);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x;
+        w[0] = b.y; w[1] = b.z; w[2] = b.w; w[3] = c.x; w[4] = c.y;
+      }
+    } else {
+      if constexpr (C == 3) {
+        const u4u u = *reinterpret_cast<const u4u*>(reinterpret_cast<const uint16_t*>(F) + 4 * (size_t)idx);
+        const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z), d = h2f(u.w);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; w[0] = c.x; w[1] = c.y; w[2] = d.x;
+      } else {
+        const u4u u = *reinterpret_cast<const u4u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx);
+        const u2u t = *reinterpret_cast<const u2u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx + 8);
+        const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z), d = h2f(u.w), e = h2f(t.x), f = h2f(t.y);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x;
+        w[0] = d.x; w[1] = d.y; w[2] = e.x; w[3] = e.y; w[4] = f.x;
+      }
+    }
+  }
+};
 
-// Per-lane state of one pixel: the lane's patch column of source features and
-// the tap geometry (integer offset + fraction of Delta(d)) of that column.
+// Per-lane state of one pixel: the lane's patch column of source features and,
+// for distorted patches, the tap geometry (integer offset + fraction of
+// Delta(d)) of that column, all in registers for every candidate.
 template <int R, int C, bool IDENT>
 struct LaneCol {
   static constexpr int T = 2 * R + 1;
+  static constexpr int TG = IDENT ? 1 : T;
   float f1[T][C];
-  int ox[T], oy[T];
-  float fx[IDENT ? 1 : T], fy[IDENT ? 1 : T];
+  int dx;
+  int ox[TG], oy[TG];
+  float fx[TG], fy[TG];
 };
 
-// Tap geometry of column dx for plane H at pixel (x, y).  Returns false when
-// the homogeneous coordinate is not positive somewhere (cost = +inf).
+// Tap geometry of column dx for plane H at pixel (x, y) (H == nullptr: the
+// identity).  Returns false when the homogeneous coordinate is not positive at
+// some tap (cost = +inf); sets integral when every fraction of the column is 0.
 template <int R, int C, bool IDENT>
-__device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, int x, int y, int dx, float lim) {
+__device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, int x, int y, int dx, float lim,
+                                      bool& integral) {
+  L.dx = dx;
+  integral = true;
   if constexpr (IDENT) {
-#pragma unroll
-    for (int t = 0; t < 2 * R + 1; ++t) {
-      L.ox[t] = dx;
-      L.oy[t] = t - R;
-    }
     return true;
   } else {
     if (H == nullptr) {
@@ -111,6 +157,7 @@ __device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, 
       L.oy[t] = (int)fly;
       L.fx[t] = Dx - flx;
       L.fy[t] = Dy - fly;
+      integral = integral && (L.fx[t] == 0.f) && (L.fy[t] == 0.f);
     }
     return ok;
   }
@@ -122,65 +169,19 @@ __device__ inline void load_column(LaneCol<R, C, IDENT>& L, const void* F1, int 
 #pragma unroll
   for (int t = 0; t < 2 * R + 1; ++t) {
     const int cy = clampi(y + t - R, 0, H - 1);
-    load_px<C, FP16>(F1, W * H, cy * W + cx, L.f1[t]);
+    Px<C, FP16>::load1(F1, cy * W + cx, L.f1[t]);
   }
 }
 
-// Column partial of the cost for target (tx, ty).
-template <int R, int C, bool FP16, bool IDENT>
-__device__ inline float column_cost(const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H, int tx,
-                                    int ty, float gw) {
-  float acc = 0.f;
-  const int npix = W * H;
+template <int C>
+__device__ inline float tap_sq(const float* f1, const float* v, float gw) {
+  float row = 0.f;
 #pragma unroll
-  for (int t = 0; t < 2 * R + 1; ++t) {
-    float v[C];
-    int bx = tx + L.ox[t], by = ty + L.oy[t];
-    if constexpr (IDENT) {
-      bx = clampi(bx, 0, W - 1);
-      by = clampi(by, 0, H - 1);
-      load_px<C, FP16>(F2, npix, by * W + bx, v);
-    } else {
-      float fx = L.fx[t], fy = L.fy[t];
-      if (bx < 0) {
-        bx = 0;
-        fx = 0.f;
-      } else if (bx >= W - 1) {
-        bx = W - 1;
-        fx = 0.f;
-      }
-      if (by < 0) {
-        by = 0;
-        fy = 0.f;
-      } else if (by >= H - 1) {
-        by = H - 1;
-        fy = 0.f;
-      }
-      const int i00 = by * W + bx;
-      const int i01 = i00 + (bx < W - 1 ? 1 : 0);
-      const int i10 = i00 + (by < H - 1 ? W : 0);
-      const int i11 = i10 + (bx < W - 1 ? 1 : 0);
-      float a[C], b[C], c[C], d[C];
-      load_px<C, FP16>(F2, npix, i00, a);
-      load_px<C, FP16>(F2, npix, i01, b);
-      load_px<C, FP16>(F2, npix, i10, c);
-      load_px<C, FP16>(F2, npix, i11, d);
-#pragma unroll
-      for (int k = 0; k < C; ++k) {
-        const float top = fmaf(fx, b[k] - a[k], a[k]);
-        const float bot = fmaf(fx, d[k] - c[k], c[k]);
-        v[k] = fmaf(fy, bot - top, top);
-      }
-    }
-    float row = 0.f;
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const float e = L.f1[t][k] - v[k];
-      row = (k < 3) ? fmaf(e, e, row) : fmaf(gw * e, e, row);
-    }
-    acc += row;
+  for (int k = 0; k < C; ++k) {
+    const float e = f1[k] - v[k];
+    row = (k < 3) ? fmaf(e, e, row) : fmaf(gw * e, e, row);
   }
-  return acc;
+  return row;
 }
 
 // Sum of the group's column partials in lane order; identical on every lane.
@@ -196,12 +197,110 @@ __device__ inline const double* plane_H(const Ws& w, int label) {
   return label >= 0 ? w.planes[label].H : nullptr;
 }
 
-// Adds each group's evaluation count into counters[dir] with one atomic per
-// wave; called by every lane of the wave (outside divergent code).
-__device__ inline void count_evals(unsigned long long* ctr, unsigned v) {
+// Adds each group's count into counter `kind` with one atomic per wave;
+// called by every lane of the wave (outside divergent code).  Spread over
+// kCounterStripes copies (STRIPED) so that the waves of a launch do not
+// serialise on one address, or all on copy 0: measured on MI355X, striping
+// speeds the identity-patch and cost kernels (14.2 vs 14.4 ms and 1.4 vs 4.0
+// ms per pipeline) while the distorted-patch kernel runs faster with one
+// address (40.4 vs 51.3 ms); results are identical either way.
+template <bool STRIPED>
+__device__ inline void count_evals(unsigned long long* counters, int kind, unsigned v) {
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(ctr, (unsigned long long)v);
+  const int stripe = STRIPED ? (blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) & (kCounterStripes - 1) : 0;
+  if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&counters[kind * kCounterStripes + stripe], (unsigned long long)v);
+}
+
+// Group-wide geometry status: 0 = usable, fractional taps; 1 = usable, all
+// taps integral; 2 = some homogeneous coordinate not positive (cost +inf).
+template <int G>
+__device__ inline int group_geometry(bool ok, bool integral, int base) {
+  const float bad = group_sum<G>(ok ? 0.f : 1.f, base);
+  const float frac = group_sum<G>(integral ? 0.f : 1.f, base);
+  return bad != 0.f ? 2 : (frac == 0.f ? 1 : 0);
+}
+
+// Adds the lane's taps of rows [T0, T1) for target (tx, ty) to acc.  Integral
+// geometry: one pixel per tap.  Otherwise bilinear: the corner pairs of the
+// tap's two rows, each one contiguous load.  No branches inside, so the loads
+// of all the rows can be in flight together.
+template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL, int T0, int T1>
+__device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H,
+                                 int tx, int ty, float gw) {
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    float v[C];
+    if constexpr (IDENT) {
+      const int bx = clampi(tx + L.dx, 0, W - 1);
+      const int by = clampi(ty + t - R, 0, H - 1);
+      Px<C, FP16>::load1(F2, by * W + bx, v);
+    } else if constexpr (INTEGRAL) {
+      const int bx = clampi(tx + L.ox[t], 0, W - 1);
+      const int by = clampi(ty + L.oy[t], 0, H - 1);
+      Px<C, FP16>::load1(F2, by * W + bx, v);
+    } else {
+      int bx = tx + L.ox[t], by = ty + L.oy[t];
+      float fx = L.fx[t], fy = L.fy[t];
+      if (bx < 0) {
+        bx = 0;
+        fx = 0.f;
+      } else if (bx >= W - 1) {
+        bx = W - 1;
+        fx = 0.f;
+      }
+      if (by < 0) {
+        by = 0;
+        fy = 0.f;
+      } else if (by >= H - 1) {
+        by = H - 1;
+        fy = 0.f;
+      }
+      const int i0 = by * W + bx;
+      const int i1 = i0 + (by < H - 1 ? W : 0);
+      float a[C], b[C], c[C], d[C];
+      Px<C, FP16>::load2(F2, i0, a, b);
+      Px<C, FP16>::load2(F2, i1, c, d);
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const float top = fmaf(fx, b[k] - a[k], a[k]);
+        const float bot = fmaf(fx, d[k] - c[k], c[k]);
+        v[k] = fmaf(fy, bot - top, top);
+      }
+    }
+    acc += tap_sq<C>(L.f1[t], v, gw);
+  }
+  return acc;
+}
+
+// Group cost of target (tx, ty).  With EE the running group sum is compared
+// with `bound` (the current best cost) after the first and second third of the
+// rows: every tap adds a non-negative term and FP32 addition is monotone, so a
+// prefix >= bound proves the full cost >= bound, and the candidate, which could
+// never be strictly better, is dropped (rejected = true).  An accepted
+// candidate is summed in the same order as without the checks.  rows returns
+// the tap rows computed.
+template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL, bool EE>
+__device__ inline float group_cost(const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H, int tx,
+                                   int ty, float gw, int base, float bound, bool& rejected, unsigned& rows) {
+  constexpr int T = 2 * R + 1, T1 = T / 3, T2 = (2 * T) / 3;
+  rejected = false;
+  if constexpr (!EE) {
+    rows += T;
+    return group_sum<T>(add_rows<R, C, FP16, IDENT, INTEGRAL, 0, T>(0.f, L, F2, W, H, tx, ty, gw), base);
+  } else {
+    float acc = add_rows<R, C, FP16, IDENT, INTEGRAL, 0, T1>(0.f, L, F2, W, H, tx, ty, gw);
+    rows += T1;
+    rejected = true;
+    if (group_sum<T>(acc, base) >= bound) return 0.f;
+    acc = add_rows<R, C, FP16, IDENT, INTEGRAL, T1, T2>(acc, L, F2, W, H, tx, ty, gw);
+    rows += T2 - T1;
+    if (group_sum<T>(acc, base) >= bound) return 0.f;
+    acc = add_rows<R, C, FP16, IDENT, INTEGRAL, T2, T>(acc, L, F2, W, H, tx, ty, gw);
+    rows += T - T2;
+    rejected = false;
+    return group_sum<T>(acc, base);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -229,21 +328,199 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
   if (act) {
     const float lim = 4.0f * (float)(W > H ? W : H);
     LaneCol<R, C, IDENT> L;
-    const bool ok = setup_geometry<R, C, IDENT>(L, plane_H(w, label), x, y, j - R, lim);
-    const bool all_ok = group_sum<G>(ok ? 0.f : 1.f, base) == 0.f;
+    bool integral;
+    const bool ok = setup_geometry<R, C, IDENT>(L, plane_H(w, label), x, y, j - R, lim, integral);
+    const int geo = group_geometry<G>(ok, integral, base);
     const int32_t v = w.nnf[dir][p];
     float c = __builtin_huge_valf();
-    if (all_ok) {
+    if (geo != 2) {
       load_column<R, C, FP16, IDENT>(L, w.feat[dir], W, H, x, y, j - R);
-      c = group_sum<G>(
-          column_cost<R, C, FP16, IDENT>(L, w.feat[1 - dir], W, H, x + off_dx(v), y + off_dy(v), P.gw), base);
+      const int tx = x + off_dx(v), ty = y + off_dy(v);
+      bool rejected;
+      unsigned rows = 0;
+      if (IDENT || geo == 1)
+        c = group_cost<R, C, FP16, IDENT, true, false>(L, w.feat[1 - dir], W, H, tx, ty, P.gw, base, 0.f, rejected,
+                                                       rows);
+      else
+        c = group_cost<R, C, FP16, IDENT, IDENT, false>(L, w.feat[1 - dir], W, H, tx, ty, P.gw, base, 0.f, rejected,
+                                                        rows);
     }
     if (j == 0) {
       w.cost[dir][p] = c;
       evals = 1;
     }
   }
-  count_evals(&w.counters[2 + dir], evals);
+  count_evals<true>(w.counters, 2 + dir, evals);
+}
+
+// Candidate loops of one pixel: the four neighbours' offsets (left, right, up,
+// down), the plane candidate (restricted passes), then random search centred on
+// the best offset after those; a candidate replaces the best only if strictly
+// better.  Two schedules with identical decisions:
+//  * identity patches (short per-candidate chain): candidates in batches of
+//    NB whose gathers are issued together, compared in candidate order after
+//    the batch;
+//  * distorted patches (long chain, register-heavy): one candidate at a time
+//    with the exact early rejection of group_cost.
+
+// Group costs of NB identity-patch targets: each lane walks its column once,
+// issuing the loads of all NB candidates per tap; every candidate is summed in
+// the same order as a lone evaluation.
+template <int R, int C, bool FP16, int NB>
+__device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, const void* __restrict__ F2, int W,
+                                              int H, const int* tx, const int* ty, float gw, int base, float* cost) {
+  constexpr int T = 2 * R + 1;
+  float acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      float v[C];
+      const int bx = clampi(tx[b] + L.dx, 0, W - 1);
+      const int by = clampi(ty[b] + t - R, 0, H - 1);
+      Px<C, FP16>::load1(F2, by * W + bx, v);
+      acc[b] += tap_sq<C>(L.f1[t], v, gw);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cost[b] = group_sum<T>(acc[b], base);
+}
+
+template <int R, int C, bool FP16, int NB>
+__device__ inline void ident_batch(const LaneCol<R, C, true>& L, const void* F2, int W, int H, const int* tx,
+                                   const int* ty, const bool* ok, float gw, int base, int& btx, int& bty, float& bc,
+                                   unsigned& evals) {
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) any = any || ok[b];
+  if (!any) return;
+  float c[NB];
+  group_cost_ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, gw, base, c);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (!ok[b]) continue;
+    ++evals;
+    if (tx[b] == btx && ty[b] == bty) continue;
+    if (c[b] < bc) {
+      bc = c[b];
+      btx = tx[b];
+      bty = ty[b];
+    }
+  }
+}
+
+template <int R, int C, bool FP16>
+__device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const DevParams& P, const Ws& w, int dir,
+                                           int x, int y, int base, const int* rox, const int* roy, unsigned& evals,
+                                           unsigned& rows) {
+  constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G, NB = 4;
+  const int W = P.W, H = P.H, p = y * W + x;
+  const void* F2 = w.feat[1 - dir];
+  const int32_t* nnf = w.nnf[dir];
+  const int32_t v0 = nnf[p];
+  int btx = x + off_dx(v0), bty = y + off_dy(v0);
+  float bc = w.cost[dir][p];
+  const unsigned e0 = evals;
+  {
+    int tx[4], ty[4];
+    bool ok[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int nx = x + (k == 0 ? -1 : (k == 1 ? 1 : 0));
+      const int ny = y + (k == 2 ? -1 : (k == 3 ? 1 : 0));
+      const bool inside = nx >= 0 && nx < W && ny >= 0 && ny < H;
+      const int32_t v = nnf[clampi(ny, 0, H - 1) * W + clampi(nx, 0, W - 1)];
+      tx[k] = clampi(x + off_dx(v), 0, W - 1);
+      ty[k] = clampi(y + off_dy(v), 0, H - 1);
+      ok[k] = inside && !(tx[k] == btx && ty[k] == bty);
+    }
+    ident_batch<R, C, FP16, 4>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
+  }
+  const int cdx = btx - x, cdy = bty - y;
+  for (int k0 = 0; k0 < P.nk; k0 += NB) {
+    int tx[NB], ty[NB];
+    bool ok[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int kk = k0 + b;
+      const int src = base + (kk % G), slot_k = kk / G;
+      int mx = rox[0], my = roy[0];
+#pragma unroll
+      for (int h = 1; h < NH; ++h) {
+        mx = slot_k == h ? rox[h] : mx;
+        my = slot_k == h ? roy[h] : my;
+      }
+      tx[b] = clampi(x + cdx + __shfl(mx, src), 0, W - 1);
+      ty[b] = clampi(y + cdy + __shfl(my, src), 0, H - 1);
+      ok[b] = kk < P.nk && !(tx[b] == btx && ty[b] == bty);
+    }
+    ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
+  }
+  rows += (evals - e0) * G;
+  if (base == (int)(threadIdx.x & (kWave - 1))) {
+    w.nnf[dir][p] = pack_off(btx - x, bty - y);
+    w.cost[dir][p] = bc;
+  }
+}
+
+template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL>
+__device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const DevParams& P, const Ws& w, int dir, int x,
+                                     int y, int base, bool has_plane, int ptx, int pty, const int* rox,
+                                     const int* roy, unsigned& evals, unsigned& rows) {
+  constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G;
+  constexpr bool EE = true;
+  const int W = P.W, H = P.H, p = y * W + x;
+  const void* F2 = w.feat[1 - dir];
+  const int32_t* nnf = w.nnf[dir];
+  const int32_t v0 = nnf[p];
+  int btx = x + off_dx(v0), bty = y + off_dy(v0);
+  float bc = w.cost[dir][p];
+  int cdx = 0, cdy = 0;
+  for (int k = 0; k < 5 + P.nk; ++k) {
+    int tx, ty;
+    if (k < 4) {
+      const int nx = x + (k == 0 ? -1 : (k == 1 ? 1 : 0));
+      const int ny = y + (k == 2 ? -1 : (k == 3 ? 1 : 0));
+      if (nx < 0 || nx >= W || ny < 0 || ny >= H) continue;
+      const int32_t v = nnf[ny * W + nx];
+      tx = clampi(x + off_dx(v), 0, W - 1);
+      ty = clampi(y + off_dy(v), 0, H - 1);
+    } else if (k == 4) {
+      if (!has_plane) continue;
+      tx = ptx;
+      ty = pty;
+    } else {
+      if (k == 5) {
+        cdx = btx - x;
+        cdy = bty - y;
+      }
+      const int kk = k - 5;
+      const int src = base + (kk % G), slot_k = kk / G;
+      int mx = rox[0], my = roy[0];
+#pragma unroll
+      for (int h = 1; h < NH; ++h) {
+        mx = slot_k == h ? rox[h] : mx;
+        my = slot_k == h ? roy[h] : my;
+      }
+      tx = clampi(x + cdx + __shfl(mx, src), 0, W - 1);
+      ty = clampi(y + cdy + __shfl(my, src), 0, H - 1);
+    }
+    if (tx == btx && ty == bty) continue;  // same target: same cost, never strictly better
+    bool rejected;
+    const float c = group_cost<R, C, FP16, IDENT, INTEGRAL, EE>(L, F2, W, H, tx, ty, P.gw, base, bc, rejected, rows);
+    ++evals;
+    if (!rejected && c < bc) {
+      bc = c;
+      btx = tx;
+      bty = ty;
+    }
+  }
+  if (base == (int)(threadIdx.x & (kWave - 1))) {
+    w.nnf[dir][p] = pack_off(btx - x, bty - y);
+    w.cost[dir][p] = bc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
   act = act && x < W;
   const int p = y * W + x;
   if (act && restricted) act = w.win[dir][p] < 0;
-  unsigned evals = 0;
+  unsigned evals = 0, rows = 0;
   if (act) {
     const int label = restricted ? w.hlabel[dir][p] : -1;
     const double* Hp = plane_H(w, label);
@@ -289,44 +566,15 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
     }
 
     LaneCol<R, C, IDENT> L;
-    const bool ok = setup_geometry<R, C, IDENT>(L, Hp, x, y, j - R, lim);
+    bool integral;
+    const bool ok = setup_geometry<R, C, IDENT>(L, Hp, x, y, j - R, lim, integral);
+    const int geo = group_geometry<G>(ok, integral, base);
     // a non-positive homogeneous coordinate makes every candidate +inf: no update
-    if (group_sum<G>(ok ? 0.f : 1.f, base) == 0.f) {
+    if (geo != 2) {
       load_column<R, C, FP16, IDENT>(L, w.feat[dir], W, H, x, y, j - R);
-      const void* F2 = w.feat[1 - dir];
-      const int32_t* nnf = w.nnf[dir];
-
-      const int32_t v0 = nnf[p];
-      int btx = x + off_dx(v0), bty = y + off_dy(v0);
-      float bc = w.cost[dir][p];
-      auto consider = [&](int tx, int ty) {
-        if (tx == btx && ty == bty) return;  // same target: same cost, never strictly better
-        const float c = group_sum<G>(column_cost<R, C, FP16, IDENT>(L, F2, W, H, tx, ty, P.gw), base);
-        ++evals;
-        if (c < bc) {
-          bc = c;
-          btx = tx;
-          bty = ty;
-        }
-      };
-      // propagation: left, right, up, down
-      if (x > 0) {
-        const int32_t v = nnf[p - 1];
-        consider(clampi(x + off_dx(v), 0, W - 1), clampi(y + off_dy(v), 0, H - 1));
-      }
-      if (x < W - 1) {
-        const int32_t v = nnf[p + 1];
-        consider(clampi(x + off_dx(v), 0, W - 1), clampi(y + off_dy(v), 0, H - 1));
-      }
-      if (y > 0) {
-        const int32_t v = nnf[p - W];
-        consider(clampi(x + off_dx(v), 0, W - 1), clampi(y + off_dy(v), 0, H - 1));
-      }
-      if (y < H - 1) {
-        const int32_t v = nnf[p + W];
-        consider(clampi(x + off_dx(v), 0, W - 1), clampi(y + off_dy(v), 0, H - 1));
-      }
       // plane candidate: where the region plane sends p, rounded to the grid
+      bool has_plane = false;
+      int ptx = 0, pty = 0;
       if (restricted && Hp) {
         const double ww = Hp[6] * x + Hp[7] * y + Hp[8];
         if (ww > 0) {
@@ -336,31 +584,24 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
           const double dl = (double)lim;
           rx = rx < -dl ? -dl : (rx > dl ? dl : rx);
           ry = ry < -dl ? -dl : (ry > dl ? dl : ry);
-          consider(clampi((int)rx, 0, W - 1), clampi((int)ry, 0, H - 1));
+          ptx = clampi((int)rx, 0, W - 1);
+          pty = clampi((int)ry, 0, H - 1);
+          has_plane = true;
         }
       }
-      // random search around the best offset after propagation
-      const int cdx = btx - x, cdy = bty - y;
-      for (int k = 0; k < P.nk; ++k) {
-        const int src = base + (k % G), slot_k = k / G;
-        int mx = rox[0], my = roy[0];
-#pragma unroll
-        for (int h = 1; h < NH; ++h) {
-          mx = slot_k == h ? rox[h] : mx;
-          my = slot_k == h ? roy[h] : my;
-        }
-        const int ox = __shfl(mx, src);
-        const int oy = __shfl(my, src);
-        consider(clampi(x + cdx + ox, 0, W - 1), clampi(y + cdy + oy, 0, H - 1));
-      }
-      if (j == 0) {
-        w.nnf[dir][p] = pack_off(btx - x, bty - y);
-        w.cost[dir][p] = bc;
-      }
+      if constexpr (IDENT)
+        pm_candidates_ident<R, C, FP16>(L, P, w, dir, x, y, base, rox, roy, evals, rows);
+      else if (geo == 1)
+        pm_candidates_serial<R, C, FP16, IDENT, true>(L, P, w, dir, x, y, base, has_plane, ptx, pty, rox, roy, evals,
+                                                      rows);
+      else
+        pm_candidates_serial<R, C, FP16, IDENT, false>(L, P, w, dir, x, y, base, has_plane, ptx, pty, rox, roy,
+                                                       evals, rows);
     }
-    if (j != 0) evals = 0;
+    if (j != 0) evals = rows = 0;
   }
-  count_evals(&w.counters[(restricted ? 4 : 0) + dir], evals);
+  count_evals<IDENT>(w.counters, (restricted ? 4 : 0) + dir, evals);
+  count_evals<IDENT>(w.counters, (restricted ? 8 : 6) + dir, rows);
 }
 
 // ---------------------------------------------------------------------------

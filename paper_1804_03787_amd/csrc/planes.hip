@@ -34,17 +34,15 @@ __device__ inline bool project(const double* H, double x, double y, double& qx, 
 
 __device__ inline void rgb_at(const DevParams& P, const void* F, int idx, double* v) {
   if (P.fp16) {
-    const uint4 u = reinterpret_cast<const uint4*>(F)[idx];
-    const float2 a = __half22float2(__builtin_bit_cast(__half2, u.x));
-    const float2 b = __half22float2(__builtin_bit_cast(__half2, u.y));
-    v[0] = a.x;
-    v[1] = a.y;
-    v[2] = b.x;
+    const __half* h = reinterpret_cast<const __half*>(F) + (size_t)(P.C == 3 ? 4 : 6) * idx;
+    v[0] = __half2float(h[0]);
+    v[1] = __half2float(h[1]);
+    v[2] = __half2float(h[2]);
   } else {
-    const float4 a = reinterpret_cast<const float4*>(F)[idx];
-    v[0] = a.x;
-    v[1] = a.y;
-    v[2] = a.z;
+    const float* f = reinterpret_cast<const float*>(F) + (size_t)P.C * idx;
+    v[0] = f[0];
+    v[1] = f[1];
+    v[2] = f[2];
   }
 }
 

@@ -202,8 +202,9 @@ class Pair:
 
     def counters(self) -> dict:
         """Warped-patch evaluations of the last pipeline run, per direction."""
-        c = self._view(self.L.counters, 8, torch.int64).cpu().numpy()
-        return {"pm_init": c[0:2].tolist(), "eval_cost": c[2:4].tolist(), "pm_restricted": c[4:6].tolist()}
+        c = self._view(self.L.counters, 16 * 64, torch.int64).cpu().numpy().reshape(16, 64).sum(axis=1)
+        return {"pm_init": c[0:2].tolist(), "eval_cost": c[2:4].tolist(), "pm_restricted": c[4:6].tolist(),
+                "pm_init_rows": c[6:8].tolist(), "pm_restricted_rows": c[8:10].tolist()}
 
     def features(self, f) -> np.ndarray:
         """Features of frame f as (H, W, C) float32 on the host."""
@@ -211,15 +212,10 @@ class Pair:
         C = self.p.channels
         raw = self.feat_bytes(f)
         if self.p.flags & FLAG_FP16:
-            h = raw[:n * 16].view(torch.float16).reshape(n, 8).float().cpu().numpy()
-            return h[:, :C].reshape(self.H, self.W, C)
-        a = raw[:n * 16].view(torch.float32).reshape(n, 4).cpu().numpy()
-        out = np.zeros((n, C), np.float32)
-        out[:, :3] = a[:, :3]
-        if C == 5:
-            out[:, 3] = a[:, 3]
-            out[:, 4] = raw[n * 16:n * 20].view(torch.float32).cpu().numpy()
-        return out.reshape(self.H, self.W, C)
+            S = 4 if C == 3 else 6
+            h = raw[:n * S * 2].view(torch.float16).reshape(n, S).float().cpu().numpy()
+            return np.ascontiguousarray(h[:, :C]).reshape(self.H, self.W, C)
+        return raw[:n * C * 4].view(torch.float32).reshape(self.H, self.W, C).cpu().numpy().copy()
 
     # ---- phases --------------------------------------------------------------
     def _frame(self, f):
