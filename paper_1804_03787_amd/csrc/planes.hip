@@ -264,18 +264,189 @@ __device__ inline int pt_x(uint32_t v) { return (int)(v & 0xffffu); }
 __device__ inline int pt_y(uint32_t v) { return (int)(v >> 16); }
 
 // ---------------------------------------------------------------------------
-// RANSAC: one workgroup per (window, direction).  Points live in LDS; each
-// thread draws, solves and scores its own hypotheses against all points.
+// RANSAC: one workgroup per (window, direction).
+//
+// 1. The window's point list (source pixel, NNF target; row-major, stage 2 only
+//    the unassigned pixels) is compacted into LDS.
+// 2. Hypotheses are made 256 at a time, one per thread: sample, degeneracy
+//    test, normalised DLT; the batch's 8 coefficients per hypothesis go to LDS.
+// 3. Scoring is point-major: each wave takes a strided share of the points,
+//    4 per lane, converted to FP64 once, and tests them against every valid
+//    hypothesis of the batch (coefficients broadcast from LDS); per-hypothesis
+//    counts are ballot popcounts, gathered into lanes and added into LDS.
+// 4. The winner (largest count, lowest index) is refitted by least squares on
+//    its inliers.  The inliers are compacted in list order; the centroid sums
+//    are integer sums (exact in any order); the mean-distance and
+//    normal-equation sums keep the sequential order of the definition: the
+//    per-inlier terms are produced by waves 1-3 into a double buffer while
+//    wave 0 adds them, one lane per distinct sum, in list order.
+// 5. The refit's support is recounted over the window (read again from the
+//    NNF) and kept when it does not lose support.
 // ---------------------------------------------------------------------------
+constexpr int kScorePts = 4;    // points per lane while scoring
+constexpr int kMdChunk = 192;   // inliers per mean-distance chunk: one per producer thread
+constexpr int kNeChunk = 32;    // inliers per normal-equation chunk: 6 producer threads each
+constexpr int kNeSlots = 40;    // doubles per inlier in a normal-equation chunk
+constexpr int kNeSums = 29;     // distinct normal-equation sums (below)
+constexpr int kNeZero = 37;     // slot holding +0 (the second term of one-term sums)
+constexpr int kAuxDoubles = 2 * kNeChunk * kNeSlots;
+static_assert(kAuxDoubles >= kBlock * 8, "hypothesis batch must fit the aux area");
+static_assert(kAuxDoubles >= 2 * 2 * kMdChunk, "mean-distance buffers must fit the aux area");
+static_assert(kMdChunk == kBlock - kWave && kNeChunk * 6 == kBlock - kWave, "producers are waves 1-3");
+
+// Inlier test against 8 coefficients with h8 = 1 (the DLT and the refit
+// normalise to it), same operations as ransac_inlier.
+__device__ inline bool inlier8(const double* H, double x, double y, double qx, double qy, double tau2) {
+  const double w = H[6] * x + H[7] * y + 1.0;
+  const double u = H[0] * x + H[1] * y + H[2];
+  const double v = H[3] * x + H[4] * y + H[5];
+  const double ex = u - w * qx, ey = v - w * qy;
+  const double e2 = ex * ex + ey * ey;
+  const double t = tau2 * w * w;
+  return (w > 0) && (e2 < t);
+}
+
+// Hypothesis h of window b: partial Fisher-Yates over a virtual identity
+// permutation of the n points, degeneracy test, normalised DLT.
+__device__ inline bool make_hypothesis(const DevParams& P, int b, int h, int n, uint64_t w3, const uint32_t* src,
+                                       const uint32_t* dst, double* Hout) {
+  uint64_t c[4] = {(uint64_t)b, (uint64_t)h, 0, w3};
+  philox4x64(c, P.seed, 0);
+  int key[8], val[8], nm = 0, sel[4];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) key[m] = val[m] = -1;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int rj = j + draw_below(c[j], (uint32_t)(n - j));
+    int vj = j, vr = rj, fj = -1, fr = -1;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (m < nm && key[m] == j) {
+        vj = val[m];
+        fj = m;
+      }
+      if (m < nm && key[m] == rj) {
+        vr = val[m];
+        fr = m;
+      }
+    }
+    if (fj < 0) fj = nm++;
+    if (fr < 0) fr = nm++;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (m == fj) {
+        key[m] = j;
+        val[m] = vr;
+      }
+      if (m == fr) {
+        key[m] = rj;
+        val[m] = vj;
+      }
+    }
+    sel[j] = vr;
+  }
+  int SX[4], SY[4], DX[4], DY[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a = src[sel[j]], d = dst[sel[j]];
+    SX[j] = pt_x(a);
+    SY[j] = pt_y(a);
+    DX[j] = pt_x(d);
+    DY[j] = pt_y(d);
+  }
+  bool degen = false;
+  degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[2], SY[2]);
+  degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[3], SY[3]);
+  degen = degen || collinear(SX[0], SY[0], SX[2], SY[2], SX[3], SY[3]);
+  degen = degen || collinear(SX[1], SY[1], SX[2], SY[2], SX[3], SY[3]);
+  degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[2], DY[2]);
+  degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[3], DY[3]);
+  degen = degen || collinear(DX[0], DY[0], DX[2], DY[2], DX[3], DY[3]);
+  degen = degen || collinear(DX[1], DY[1], DX[2], DY[2], DX[3], DY[3]);
+  if (degen) return false;
+  const double sx[4] = {(double)SX[0], (double)SX[1], (double)SX[2], (double)SX[3]};
+  const double sy[4] = {(double)SY[0], (double)SY[1], (double)SY[2], (double)SY[3]};
+  const double ddx[4] = {(double)DX[0], (double)DX[1], (double)DX[2], (double)DX[3]};
+  const double ddy[4] = {(double)DY[0], (double)DY[1], (double)DY[2], (double)DY[3]};
+  return dlt4(sx, sy, ddx, ddy, Hout);
+}
+
+// Normal-equation terms of one inlier (normalised x, y, u, v).  With
+// a0 = (x, y, 1, 0, 0, 0, -xu, -yu) and a1 = (0, 0, 0, x, y, 1, -xv, -yv), the
+// sums N[j][k] += a0[j] a0[k]; N[j][k] += a1[j] a1[k]; rhs[j] += a0[j] u;
+// rhs[j] += a1[j] v have, per inlier, at most two non-zero terms; the zero
+// products leave a sum unchanged (it starts at +0 and cannot become -0), so
+// only the non-zero terms are added.  29 distinct sums remain:
+//   0-5   N00 N01 N02 N11 N12 N22 (= N33 N34 N35 N44 N45 N55)
+//   6-11  N06 N07 N16 N17 N26 N27        12-14 rhs0 rhs1 rhs2
+//   15-20 N36 N37 N46 N47 N56 N57        21-23 rhs3 rhs4 rhs5
+//   24-28 N66 N67 N77 rhs6 rhs7 (two terms: the a0 one, then the a1 one)
+// Slot s < 29 holds the first (or only) term of sum s; slots 32-36 the second
+// term of sums 24-28; slot 37 is +0.  Each producer thread writes one part.
+__device__ inline void ne_terms(double x, double y, double u, double v, int part, double* T) {
+  const double p6 = -x * u, p7 = -y * u, q6 = -x * v, q7 = -y * v;
+  switch (part) {
+    case 0:
+      T[0] = x * x;
+      T[1] = x * y;
+      T[2] = x * 1.0;
+      T[3] = y * y;
+      T[4] = y * 1.0;
+      T[5] = 1.0;
+      break;
+    case 1:
+      T[6] = x * p6;
+      T[7] = x * p7;
+      T[8] = y * p6;
+      T[9] = y * p7;
+      T[10] = 1.0 * p6;
+      T[11] = 1.0 * p7;
+      break;
+    case 2:
+      T[12] = x * u;
+      T[13] = y * u;
+      T[14] = 1.0 * u;
+      T[21] = x * v;
+      T[22] = y * v;
+      T[23] = 1.0 * v;
+      break;
+    case 3:
+      T[15] = x * q6;
+      T[16] = x * q7;
+      T[17] = y * q6;
+      T[18] = y * q7;
+      T[19] = 1.0 * q6;
+      T[20] = 1.0 * q7;
+      break;
+    case 4:
+      T[24] = p6 * p6;
+      T[32] = q6 * q6;
+      T[25] = p6 * p7;
+      T[33] = q6 * q7;
+      T[26] = p7 * p7;
+      T[34] = q7 * q7;
+      break;
+    default:
+      T[27] = p6 * u;
+      T[35] = q6 * v;
+      T[28] = p7 * u;
+      T[36] = q7 * v;
+      T[kNeZero] = 0.0;
+      break;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
-  extern __shared__ uint32_t smem[];
+  extern __shared__ double smem_d[];
   __shared__ int s_wave[kBlock / kWave];
-  __shared__ int s_n;
+  __shared__ int s_n, s_ni, s_ok, s_cnt_r;
+  __shared__ int s_cnt[kBlock];
+  __shared__ unsigned long long s_gmask[kBlock / kWave];
   __shared__ unsigned long long s_key[kBlock / kWave];
-  __shared__ double s_H[9], s_Hr[9];
-  __shared__ double s_sum[8];
-  __shared__ double s_N[64], s_rhs[8];
-  __shared__ int s_ok, s_cnt, s_ni;
+  __shared__ unsigned long long s_isum[4];
+  __shared__ double s_H[8], s_Hr[9];
+  __shared__ double s_md[2];
+  __shared__ double s_ne[kNeSums];
 
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
   const int b = blockIdx.x, dir = blockIdx.y;
@@ -284,15 +455,21 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
   const int bw = B < W ? B : W, bh = B < Hh ? B : Hh;
   const int x0 = block_origin(W, B, b % nbx), y0 = block_origin(Hh, B, b / nbx);
   const int nmax = bw * bh;
-  uint32_t* src = smem;
-  uint32_t* dst = smem + nmax;
-  uint8_t* flag = reinterpret_cast<uint8_t*>(smem + 2 * nmax);
+  double* aux = smem_d;
+  uint32_t* src = reinterpret_cast<uint32_t*>(smem_d + kAuxDoubles);
+  uint32_t* dst = src + nmax;
   msgpm_plane* pl = &w.planes[plane_index(P, dir, level, stage, b)];
   const int32_t* nnf = w.nnf[dir];
   const int32_t* win = w.win[dir];
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-  // point list (row-major in the window; stage 2 keeps the unassigned pixels)
-  if (t == 0) s_n = 0;
+  // 1. point list
+  if (t == 0) {
+    s_n = 0;
+    s_ni = 0;
+    s_cnt_r = 0;
+  }
+  if (t < 4) s_isum[t] = 0ull;
   __syncthreads();
   for (int c0 = 0; c0 < nmax; c0 += kBlock) {
     const int i = c0 + t;
@@ -305,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
       if (stage == 2) keep = win[p] < 0;
     }
     const unsigned long long m = __ballot(keep);
-    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    const int before = __popcll(m & lt_mask);
     if (lane == 0) s_wave[wave] = __popcll(m);
     __syncthreads();
     int off = s_n;
@@ -343,220 +520,260 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
     return;
   }
 
-  // hypotheses h = t, t + 256, ...: draw 4 points (partial Fisher-Yates over a
-  // virtual identity permutation), reject degenerate samples, solve, count
+  // 2-3. hypotheses in batches of 256, point-major scoring
   const double tau2 = P.tau2;
   const uint64_t w3 = rng_word3(3, dir, level + 1, stage);
-  int my_cnt = -1, my_h = -1;
-  double myH[9];
-  for (int i = 0; i < 9; ++i) myH[i] = 0.0;
-  for (int h = t; h < P.hyps; h += kBlock) {
-    uint64_t c[4] = {(uint64_t)b, (uint64_t)h, 0, w3};
-    philox4x64(c, P.seed, 0);
-    int key[8], val[8], nm = 0, sel[4];
+  unsigned long long best = 0ull;  // (count << 32) | ~h, 0 = none
+  for (int base = 0; base < P.hyps; base += kBlock) {
+    const int h = base + t;
+    bool ok = false;
+    if (h < P.hyps) {
+      double Hx[9];
+      ok = make_hypothesis(P, b, h, n, w3, src, dst, Hx);
+      if (ok) {
 #pragma unroll
-    for (int m = 0; m < 8; ++m) key[m] = val[m] = -1;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int rj = j + draw_below(c[j], (uint32_t)(n - j));
-      int vj = j, vr = rj, fj = -1, fr = -1;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        if (m < nm && key[m] == j) {
-          vj = val[m];
-          fj = m;
-        }
-        if (m < nm && key[m] == rj) {
-          vr = val[m];
-          fr = m;
-        }
+        for (int j = 0; j < 8; ++j) aux[t * 8 + j] = Hx[j];
       }
-      if (fj < 0) fj = nm++;
-      if (fr < 0) fr = nm++;
+    }
+    s_cnt[t] = 0;
+    const unsigned long long gm = __ballot(ok);
+    if (lane == 0) s_gmask[wave] = gm;
+    __syncthreads();
+    for (int c0 = wave * kWave * kScorePts; c0 < n; c0 += kBlock * kScorePts) {
+      double X[kScorePts], Y[kScorePts], QX[kScorePts], QY[kScorePts];
+      unsigned long long vm[kScorePts];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        if (m == fj) {
-          key[m] = j;
-          val[m] = vr;
-        }
-        if (m == fr) {
-          key[m] = rj;
-          val[m] = vj;
-        }
+      for (int u = 0; u < kScorePts; ++u) {
+        const int i = c0 + u * kWave + lane;
+        const bool has = i < n;
+        const uint32_t a = has ? src[i] : 0u, d = has ? dst[i] : 0u;
+        X[u] = (double)pt_x(a);
+        Y[u] = (double)pt_y(a);
+        QX[u] = (double)pt_x(d);
+        QY[u] = (double)pt_y(d);
+        vm[u] = __ballot(has);
       }
-      sel[j] = vr;
-    }
-    int SX[4], SY[4], DX[4], DY[4];
+      for (int g = 0; g < kBlock / kWave; ++g) {
+        unsigned long long m = s_gmask[g];
+        m = ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(m >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((int)(m & 0xffffffffull));
+        if (!m) continue;
+        int tmp = 0;
+        while (m) {
+          const int j = __builtin_ctzll(m);
+          m &= m - 1ull;
+          const double* Hj = aux + (g * kWave + j) * 8;
+          double Hc[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t a = src[sel[j]], d = dst[sel[j]];
-      SX[j] = pt_x(a);
-      SY[j] = pt_y(a);
-      DX[j] = pt_x(d);
-      DY[j] = pt_y(d);
-    }
-    bool degen = false;
-    degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[2], SY[2]);
-    degen = degen || collinear(SX[0], SY[0], SX[1], SY[1], SX[3], SY[3]);
-    degen = degen || collinear(SX[0], SY[0], SX[2], SY[2], SX[3], SY[3]);
-    degen = degen || collinear(SX[1], SY[1], SX[2], SY[2], SX[3], SY[3]);
-    degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[2], DY[2]);
-    degen = degen || collinear(DX[0], DY[0], DX[1], DY[1], DX[3], DY[3]);
-    degen = degen || collinear(DX[0], DY[0], DX[2], DY[2], DX[3], DY[3]);
-    degen = degen || collinear(DX[1], DY[1], DX[2], DY[2], DX[3], DY[3]);
-    if (degen) continue;
-    const double sx[4] = {(double)SX[0], (double)SX[1], (double)SX[2], (double)SX[3]};
-    const double sy[4] = {(double)SY[0], (double)SY[1], (double)SY[2], (double)SY[3]};
-    const double ddx[4] = {(double)DX[0], (double)DX[1], (double)DX[2], (double)DX[3]};
-    const double ddy[4] = {(double)DY[0], (double)DY[1], (double)DY[2], (double)DY[3]};
-    double Hh_[9];
-    if (!dlt4(sx, sy, ddx, ddy, Hh_)) continue;
-    int cnt = 0;
-    for (int i = 0; i < n; ++i) {
-      const uint32_t a = src[i], d = dst[i];
-      cnt += ransac_inlier(Hh_, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
-    }
-    if (cnt > my_cnt) {
-      my_cnt = cnt;
-      my_h = h;
+          for (int k = 0; k < 8; ++k) Hc[k] = Hj[k];
+          int c = 0;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) myH[i] = Hh_[i];
+          for (int u = 0; u < kScorePts; ++u) c += __popcll(__ballot(inlier8(Hc, X[u], Y[u], QX[u], QY[u], tau2)) & vm[u]);
+          tmp = lane == j ? c : tmp;
+        }
+        atomicAdd(&s_cnt[g * kWave + lane], tmp);
+      }
     }
+    __syncthreads();
+    unsigned long long key = ok ? (((unsigned long long)s_cnt[t] << 32) | (0xffffffffu - (unsigned)h)) : 0ull;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const unsigned long long other = __shfl_xor(key, o);
+      key = other > key ? other : key;
+    }
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    unsigned long long bk = s_key[0];
+    for (int k = 1; k < kBlock / kWave; ++k) bk = s_key[k] > bk ? s_key[k] : bk;
+    if (bk > best) {
+      best = bk;
+      const int bh_ = (int)(0xffffffffu - (unsigned)(bk & 0xffffffffull));
+      if (bh_ == h) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s_H[j] = aux[t * 8 + j];
+      }
+    }
+    __syncthreads();
   }
-  // winner: largest count, lowest hypothesis index on ties
-  unsigned long long key = my_cnt >= 0 ? (((unsigned long long)my_cnt << 32) | (0xffffffffu - (unsigned)my_h)) : 0ull;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const unsigned long long other = __shfl_xor(key, o);
-    key = other > key ? other : key;
-  }
-  if (lane == 0) s_key[wave] = key;
-  __syncthreads();
-  unsigned long long best = s_key[0];
-  for (int k = 1; k < kBlock / kWave; ++k) best = s_key[k] > best ? s_key[k] : best;
   if (best == 0ull) {
     if (t == 0) *pl = out;
     return;
   }
   const int best_cnt = (int)(best >> 32);
-  const int best_h = (int)(0xffffffffu - (unsigned)(best & 0xffffffffu));
-  if (my_h == best_h && my_cnt >= 0) {
-    for (int i = 0; i < 9; ++i) s_H[i] = myH[i];
-  }
-  if (t == 0) {
-    s_cnt = 0;
-    s_ni = 0;
-  }
-  __syncthreads();
+  const int best_h = (int)(0xffffffffu - (unsigned)(best & 0xffffffffull));
 
-  // least-squares refit on the winner's inliers
-  int local_ni = 0;
-  for (int i = t; i < n; i += kBlock) {
-    const uint32_t a = src[i], d = dst[i];
-    const bool in = ransac_inlier(s_H, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
-    flag[i] = in ? 1 : 0;
-    local_ni += in;
+  // 4. inliers of the winner, compacted in list order; integer centroid sums
+  unsigned long long isum[4] = {0ull, 0ull, 0ull, 0ull};
+  for (int c0 = 0; c0 < n; c0 += kBlock) {
+    const int i = c0 + t;
+    const bool has = i < n;
+    const uint32_t a = has ? src[i] : 0u, d = has ? dst[i] : 0u;
+    const bool in = has && inlier8(s_H, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
+    const unsigned long long m = __ballot(in);
+    const int before = __popcll(m & lt_mask);
+    if (lane == 0) s_wave[wave] = __popcll(m);
+    if (in) {
+      isum[0] += (unsigned)pt_x(a);
+      isum[1] += (unsigned)pt_y(a);
+      isum[2] += (unsigned)pt_x(d);
+      isum[3] += (unsigned)pt_y(d);
+    }
+    __syncthreads();
+    int off = s_ni;
+    for (int k = 0; k < wave; ++k) off += s_wave[k];
+    if (in) {
+      src[off + before] = a;
+      dst[off + before] = d;
+    }
+    __syncthreads();
+    if (t == 0) s_ni += s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    __syncthreads();
   }
-  atomicAdd(&s_ni, local_ni);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    unsigned long long v = isum[k];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) atomicAdd(&s_isum[k], v);
+  }
   __syncthreads();
   const int ni = s_ni;
-  // centroids (lanes 0-3), in point-list order over the inliers
-  if (t < 4) {
-    double acc = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!flag[i]) continue;
-      const uint32_t v = (t < 2) ? src[i] : dst[i];
-      acc += (double)((t & 1) ? pt_y(v) : pt_x(v));
-    }
-    s_sum[t] = acc;
-  }
-  __syncthreads();
-  const double c1x = s_sum[0] / ni, c1y = s_sum[1] / ni, c2x = s_sum[2] / ni, c2y = s_sum[3] / ni;
-  if (t < 2) {
-    const double cx = t ? c2x : c1x, cy = t ? c2y : c1y;
-    double md = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!flag[i]) continue;
-      const uint32_t v = t ? dst[i] : src[i];
-      const double ex = (double)pt_x(v) - cx, ey = (double)pt_y(v) - cy;
-      md += sqrt(ex * ex + ey * ey);
-    }
-    s_sum[4 + t] = md;
-  }
-  __syncthreads();
-  const double md1 = s_sum[4] / ni, md2 = s_sum[5] / ni;
-  const bool norm_ok = ni >= 4 && (md1 > 0) && (md2 > 0);
-  const double s1 = sqrt(2.0) / md1, s2 = sqrt(2.0) / md2;
-  if (norm_ok && t < 44) {
-    // entry t: t < 36 -> N[j][k] with j <= k (row-major upper triangle); else rhs[t - 36]
-    int j = 0, k = 0;
-    if (t < 36) {
-      int r = t;
-      while (r >= 8 - j) {
-        r -= 8 - j;
-        ++j;
+  bool norm_ok = ni >= 4;
+  // centroids: the sums are integers below 2^53, so FP64 sums in any order equal them
+  const double c1x = (double)s_isum[0] / ni, c1y = (double)s_isum[1] / ni;
+  const double c2x = (double)s_isum[2] / ni, c2y = (double)s_isum[3] / ni;
+  double s1 = 0, s2 = 0;
+  if (norm_ok) {
+    // mean distances: lane 0 sums the source terms, lane 1 the target terms, in list order
+    const int nch = (ni + kMdChunk - 1) / kMdChunk;
+    const int tp = t - kWave;
+    auto produce = [&](int k) {
+      const int i = k * kMdChunk + tp;
+      if (i < ni) {
+        double* buf = aux + (k & 1) * 2 * kMdChunk;
+        const uint32_t a = src[i], d = dst[i];
+        const double ex = (double)pt_x(a) - c1x, ey = (double)pt_y(a) - c1y;
+        const double fx = (double)pt_x(d) - c2x, fy = (double)pt_y(d) - c2y;
+        buf[tp] = sqrt(ex * ex + ey * ey);
+        buf[kMdChunk + tp] = sqrt(fx * fx + fy * fy);
       }
-      k = j + r;
-    } else {
-      j = t - 36;
-    }
+    };
+    if (wave > 0) produce(0);
+    __syncthreads();
     double acc = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!flag[i]) continue;
-      const uint32_t a = src[i], d = dst[i];
-      const double x = s1 * ((double)pt_x(a) - c1x), y = s1 * ((double)pt_y(a) - c1y);
-      const double u = s2 * ((double)pt_x(d) - c2x), v = s2 * ((double)pt_y(d) - c2y);
-      const double a0[8] = {x, y, 1, 0, 0, 0, -x * u, -y * u};
-      const double a1[8] = {0, 0, 0, x, y, 1, -x * v, -y * v};
-      if (t < 36) {
-        acc += a0[j] * a0[k];
-        acc += a1[j] * a1[k];
-      } else {
-        acc += a0[j] * u;
-        acc += a1[j] * v;
+    for (int k = 0; k < nch; ++k) {
+      if (wave == 0) {
+        const double* col = aux + (k & 1) * 2 * kMdChunk + (lane & 1) * kMdChunk;
+        const int cnt = ni - k * kMdChunk < kMdChunk ? ni - k * kMdChunk : kMdChunk;
+        for (int j = 0; j < cnt; ++j) acc += col[j];
+      } else if (k + 1 < nch) {
+        produce(k + 1);
       }
+      __syncthreads();
     }
-    if (t < 36) {
-      s_N[j * 8 + k] = acc;
-      s_N[k * 8 + j] = acc;
-    } else {
-      s_rhs[j] = acc;
-    }
+    if (t < 2) s_md[t] = acc;
+    __syncthreads();
+    const double md1 = s_md[0] / ni, md2 = s_md[1] / ni;
+    norm_ok = (md1 > 0) && (md2 > 0);
+    s1 = sqrt(2.0) / md1;
+    s2 = sqrt(2.0) / md2;
   }
-  __syncthreads();
+  if (norm_ok) {
+    // normal equations: lane s of wave 0 owns sum s
+    const int nch = (ni + kNeChunk - 1) / kNeChunk;
+    const int tp = t - kWave;
+    auto produce = [&](int k) {
+      const int i = k * kNeChunk + tp / 6;
+      if (i < ni) {
+        double* T = aux + ((k & 1) * kNeChunk + tp / 6) * kNeSlots;
+        const uint32_t a = src[i], d = dst[i];
+        const double x = s1 * ((double)pt_x(a) - c1x), y = s1 * ((double)pt_y(a) - c1y);
+        const double u = s2 * ((double)pt_x(d) - c2x), v = s2 * ((double)pt_y(d) - c2y);
+        ne_terms(x, y, u, v, tp % 6, T);
+      }
+    };
+    if (wave > 0) produce(0);
+    __syncthreads();
+    const int s = lane < kNeSums ? lane : kNeSums - 1;
+    const int s2nd = s >= 24 ? 32 + (s - 24) : kNeZero;
+    double acc = 0;
+    for (int k = 0; k < nch; ++k) {
+      if (wave == 0) {
+        const double* T = aux + (k & 1) * kNeChunk * kNeSlots;
+        const int cnt = ni - k * kNeChunk < kNeChunk ? ni - k * kNeChunk : kNeChunk;
+        for (int j = 0; j < cnt; ++j) {
+          acc += T[j * kNeSlots + s];
+          acc += T[j * kNeSlots + s2nd];
+        }
+      } else if (k + 1 < nch) {
+        produce(k + 1);
+      }
+      __syncthreads();
+    }
+    if (t < kNeSums) s_ne[t] = acc;
+    __syncthreads();
+  }
   if (t == 0) {
     s_ok = 0;
     if (norm_ok) {
-      double A[8][8], rhs[8], h[8];
-      for (int r = 0; r < 8; ++r) {
-        rhs[r] = s_rhs[r];
-        for (int q = 0; q < 8; ++q) A[r][q] = s_N[r * 8 + q];
+      const double* S = s_ne;
+      double A[8][8], rhs[8], hsol[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) A[r][q] = 0.0;
+      const int tri[6][3] = {{0, 0, 0}, {0, 1, 1}, {0, 2, 2}, {1, 1, 3}, {1, 2, 4}, {2, 2, 5}};
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int r = tri[e][0], q = tri[e][1];
+        const double v = S[tri[e][2]];
+        A[r][q] = A[q][r] = v;
+        A[r + 3][q + 3] = A[q + 3][r + 3] = v;
       }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        A[r][6] = A[6][r] = S[6 + 2 * r];
+        A[r][7] = A[7][r] = S[7 + 2 * r];
+        A[r + 3][6] = A[6][r + 3] = S[15 + 2 * r];
+        A[r + 3][7] = A[7][r + 3] = S[16 + 2 * r];
+        rhs[r] = S[12 + r];
+        rhs[r + 3] = S[21 + r];
+      }
+      A[6][6] = S[24];
+      A[6][7] = A[7][6] = S[25];
+      A[7][7] = S[26];
+      rhs[6] = S[27];
+      rhs[7] = S[28];
       double Hr[9];
-      if (gauss8(A, rhs, h) && denormalise(h, s1, c1x, c1y, s2, c2x, c2y, Hr)) {
+      if (gauss8(A, rhs, hsol) && denormalise(hsol, s1, c1x, c1y, s2, c2x, c2y, Hr)) {
         for (int i = 0; i < 9; ++i) s_Hr[i] = Hr[i];
         s_ok = 1;
       }
     }
   }
   __syncthreads();
+
+  // 5. support of the refit over the whole window
   int final_cnt = best_cnt;
   bool use_refit = false;
   if (s_ok) {
     int local = 0;
-    for (int i = t; i < n; i += kBlock) {
-      const uint32_t a = src[i], d = dst[i];
-      local += ransac_inlier(s_Hr, (double)pt_x(a), (double)pt_y(a), (double)pt_x(d), (double)pt_y(d), tau2);
+    for (int i = t; i < nmax; i += kBlock) {
+      const int x = x0 + i % bw, y = y0 + i / bw, p = y * W + x;
+      if (stage == 2 && win[p] >= 0) continue;
+      const int32_t v = nnf[p];
+      local += ransac_inlier(s_Hr, (double)x, (double)y, (double)(x + off_dx(v)), (double)(y + off_dy(v)), tau2);
     }
-    atomicAdd(&s_cnt, local);
+    atomicAdd(&s_cnt_r, local);
     __syncthreads();
-    if (s_cnt >= best_cnt) {
+    if (s_cnt_r >= best_cnt) {
       use_refit = true;
-      final_cnt = s_cnt;
+      final_cnt = s_cnt_r;
     }
   }
   if (t == 0) {
-    for (int i = 0; i < 9; ++i) out.H[i] = use_refit ? s_Hr[i] : s_H[i];
+    for (int i = 0; i < 8; ++i) out.H[i] = use_refit ? s_Hr[i] : s_H[i];
+    out.H[8] = use_refit ? s_Hr[8] : 1.0;
     out.hyp = best_h;
     out.hyp_count = best_cnt;
     out.count = final_cnt;
@@ -751,7 +968,7 @@ size_t ransac_smem_bytes(const DevParams& P, int level) {
   const int B = P.block[level];
   const int bw = B < P.W ? B : P.W, bh = B < P.H ? B : P.H;
   const size_t n = (size_t)bw * bh;
-  return 2 * n * sizeof(uint32_t) + ((n + 15) & ~(size_t)15);
+  return kAuxDoubles * sizeof(double) + 2 * n * sizeof(uint32_t);
 }
 
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s) {
