@@ -283,7 +283,6 @@ __device__ inline int pt_y(uint32_t v) { return (int)(v >> 16); }
 // 5. The refit's support is recounted over the window (read again from the
 //    NNF) and kept when it does not lose support.
 // ---------------------------------------------------------------------------
-constexpr int kScorePts = 4;    // points per lane while scoring
 constexpr int kMdChunk = 192;   // inliers per mean-distance chunk: one per producer thread
 constexpr int kNeChunk = 32;    // inliers per normal-equation chunk: 6 producer threads each
 constexpr int kNeSlots = 40;    // doubles per inlier in a normal-equation chunk
@@ -436,6 +435,62 @@ __device__ inline void ne_terms(double x, double y, double u, double v, int part
   }
 }
 
+// Scores one batch of hypotheses.  Work items are (chunk of U * 64 points,
+// group of 64 hypotheses) pairs dealt round-robin to the waves; a lane holds U
+// points in FP64 and the per-hypothesis counts are popcounts of the ballots of
+// the two conditions of inlier8 (same operations), gathered into lane j for
+// hypothesis j of the group and added into s_cnt.
+template <int U>
+__device__ inline void score_batch(const double* aux, const unsigned long long* s_gmask, int* s_cnt, int ngroups,
+                                   const uint32_t* src, const uint32_t* dst, int n, double tau2, int wave,
+                                   int lane) {
+  const int nchunks = (n + U * kWave - 1) / (U * kWave);
+  const int nitems = nchunks * ngroups;
+  for (int item = wave; item < nitems; item += kBlock / kWave) {
+    const int chunk = item / ngroups, g = item - chunk * ngroups;
+    unsigned long long m = s_gmask[g];
+    m = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(m >> 32)) << 32) |
+        (unsigned)__builtin_amdgcn_readfirstlane((int)(m & 0xffffffffull));
+    if (!m) continue;
+    double X[U], Y[U], QX[U], QY[U];
+    unsigned long long vm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = chunk * U * kWave + u * kWave + lane;
+      const bool has = i < n;
+      const uint32_t a = has ? src[i] : 0u, d = has ? dst[i] : 0u;
+      X[u] = (double)pt_x(a);
+      Y[u] = (double)pt_y(a);
+      QX[u] = (double)pt_x(d);
+      QY[u] = (double)pt_y(d);
+      vm[u] = __ballot(has);
+    }
+    int tmp = 0;
+    while (m) {
+      const int j = __builtin_ctzll(m);
+      m &= m - 1ull;
+      const double* H = aux + (g * kWave + j) * 8;
+      double Hc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) Hc[k] = H[k];
+      int c = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double w = Hc[6] * X[u] + Hc[7] * Y[u] + 1.0;
+        const double uu = Hc[0] * X[u] + Hc[1] * Y[u] + Hc[2];
+        const double vv = Hc[3] * X[u] + Hc[4] * Y[u] + Hc[5];
+        const double ex = uu - w * QX[u], ey = vv - w * QY[u];
+        const double e2 = ex * ex + ey * ey;
+        const double t = tau2 * w * w;
+        const unsigned long long pos = __ballot(w > 0), close = __ballot(e2 < t);
+        c += __popcll(pos & close & vm[u]);
+      }
+      tmp = lane == j ? c : tmp;
+    }
+    atomicAdd(&s_cnt[g * kWave + lane], tmp);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
   extern __shared__ double smem_d[];
   __shared__ int s_wave[kBlock / kWave];
@@ -539,41 +594,14 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
     const unsigned long long gm = __ballot(ok);
     if (lane == 0) s_gmask[wave] = gm;
     __syncthreads();
-    for (int c0 = wave * kWave * kScorePts; c0 < n; c0 += kBlock * kScorePts) {
-      double X[kScorePts], Y[kScorePts], QX[kScorePts], QY[kScorePts];
-      unsigned long long vm[kScorePts];
-#pragma unroll
-      for (int u = 0; u < kScorePts; ++u) {
-        const int i = c0 + u * kWave + lane;
-        const bool has = i < n;
-        const uint32_t a = has ? src[i] : 0u, d = has ? dst[i] : 0u;
-        X[u] = (double)pt_x(a);
-        Y[u] = (double)pt_y(a);
-        QX[u] = (double)pt_x(d);
-        QY[u] = (double)pt_y(d);
-        vm[u] = __ballot(has);
-      }
-      for (int g = 0; g < kBlock / kWave; ++g) {
-        unsigned long long m = s_gmask[g];
-        m = ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(m >> 32)) << 32) |
-            (unsigned)__builtin_amdgcn_readfirstlane((int)(m & 0xffffffffull));
-        if (!m) continue;
-        int tmp = 0;
-        while (m) {
-          const int j = __builtin_ctzll(m);
-          m &= m - 1ull;
-          const double* Hj = aux + (g * kWave + j) * 8;
-          double Hc[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) Hc[k] = Hj[k];
-          int c = 0;
-#pragma unroll
-          for (int u = 0; u < kScorePts; ++u) c += __popcll(__ballot(inlier8(Hc, X[u], Y[u], QX[u], QY[u], tau2)) & vm[u]);
-          tmp = lane == j ? c : tmp;
-        }
-        atomicAdd(&s_cnt[g * kWave + lane], tmp);
-      }
-    }
+    const int left = P.hyps - base;
+    const int ngroups = ((left < kBlock ? left : kBlock) + kWave - 1) / kWave;
+    if (n <= kWave)
+      score_batch<1>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
+    else if (n <= 2 * kWave)
+      score_batch<2>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
+    else
+      score_batch<4>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
     __syncthreads();
     unsigned long long key = ok ? (((unsigned long long)s_cnt[t] << 32) | (0xffffffffu - (unsigned)h)) : 0ull;
 #pragma unroll
