@@ -42,6 +42,8 @@ struct Ws {
   double* tloss[2];
   msgpm_plane* planes;
   unsigned long long* counters;
+  int32_t* act[2];        // pixels a restricted half-sweep updates, per direction
+  unsigned* act_count;    // their counts [2]
 };
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }

@@ -47,6 +47,9 @@ int block_count(int n, int B) {
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
+// One direction's list of restricted half-sweep pixels (all pixels of one colour).
+uint64_t active_list_bytes(const DevParams& d) { return align256((uint64_t)((d.W + 1) / 2) * d.H * sizeof(int32_t)); }
+
 // Optional per-kind kernel timing with reusable HIP events.
 struct Timer {
   std::mutex mu;
@@ -165,6 +168,8 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     cur = align256(cur + (uint64_t)o.n_planes * sizeof(msgpm_plane));
     o.counters = cur;
     cur = align256(cur + (uint64_t)kCounterKinds * kCounterStripes * sizeof(uint64_t));
+    o.active = cur;
+    cur = align256(cur + 2 * active_list_bytes(d) + 2 * sizeof(uint32_t));
     o.total_bytes = cur;
     o.n_levels = d.n_levels;
     for (int l = 0; l < d.n_levels; ++l) {
@@ -176,7 +181,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   return MSGPM_OK;
 }
 
-Ws make_ws(const msgpm_layout& L, void* base) {
+Ws make_ws(const DevParams& P, const msgpm_layout& L, void* base) {
   char* b = static_cast<char*>(base);
   Ws w;
   for (int k = 0; k < 2; ++k) {
@@ -191,6 +196,10 @@ Ws make_ws(const msgpm_layout& L, void* base) {
   }
   w.planes = reinterpret_cast<msgpm_plane*>(b + L.planes);
   w.counters = reinterpret_cast<unsigned long long*>(b + L.counters);
+  const uint64_t lb = active_list_bytes(P);
+  w.act[0] = reinterpret_cast<int32_t*>(b + L.active);
+  w.act[1] = reinterpret_cast<int32_t*>(b + L.active + lb);
+  w.act_count = reinterpret_cast<unsigned*>(b + L.active + 2 * lb);
   return w;
 }
 
@@ -206,7 +215,7 @@ msgpm_status open_ctx(const msgpm_params* p, void* ws, void* stream, Ctx* c) {
   if (st != MSGPM_OK) return st;
   if (!ws) return fail(MSGPM_E_INVALID, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MSGPM_E_INVALID, "workspace not 256-byte aligned");
-  c->w = make_ws(c->L, ws);
+  c->w = make_ws(c->P, c->L, ws);
   c->s = static_cast<hipStream_t>(stream);
   return MSGPM_OK;
 }

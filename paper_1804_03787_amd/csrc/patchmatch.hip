@@ -524,7 +524,40 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
 }
 
 // ---------------------------------------------------------------------------
-// One red-black half-sweep over the pixels of one colour, both directions.
+// Restricted half-sweeps update only the unassigned pixels of one colour.
+// They are listed first, so that every lane group of the sweep has a pixel:
+// each wave appends its active pixels (row-major within the wave's span) at a
+// position taken from a counter.  The order of the spans in the list varies
+// between runs; the update of a pixel does not depend on it.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_active(Ws w) {
+  if (threadIdx.x < 2) w.act_count[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int colour) {
+  const int dir = blockIdx.y;
+  const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  bool act = i < (long long)Wh * H;
+  int p = 0;
+  if (act) {
+    const int y = (int)(i / Wh);
+    const int x = 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1);
+    p = y * W + x;
+    act = x < W && w.win[dir][p] < 0;
+  }
+  const unsigned long long m = __ballot(act);
+  if (m == 0ull) return;
+  unsigned base = 0u;
+  if (lane == 0) base = atomicAdd(&w.act_count[dir], (unsigned)__popcll(m));
+  base = __shfl(base, 0);
+  if (act) w.act[dir][base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+}
+
+// ---------------------------------------------------------------------------
+// One red-black half-sweep over the pixels of one colour, both directions
+// (restricted: over the listed pixels).
 // ---------------------------------------------------------------------------
 template <int R, int C, bool FP16, bool IDENT>
 __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int colour, int iter, int slot,
@@ -534,13 +567,27 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
   const int g = lane / G, j = lane - g * G, base = g * G;
   const int dir = blockIdx.y;
   const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
-  const long long i = ((long long)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + wave) * NG + g;
-  bool act = g < NG && i < (long long)Wh * H;
-  const int y = act ? (int)(i / Wh) : 0;
-  const int x = act ? 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1) : 0;
-  act = act && x < W;
+  bool act;
+  int x, y;
+  if (restricted) {
+    // only the workgroups covering the list work; each XCD takes a contiguous part
+    const unsigned cnt = w.act_count[dir];
+    constexpr unsigned per = NG * (kBlock / kWave);
+    const int nb = (int)((cnt + per - 1) / per);
+    if ((int)blockIdx.x >= nb) return;
+    const long long i = ((long long)xcd_remap(blockIdx.x, nb) * (kBlock / kWave) + wave) * NG + g;
+    act = g < NG && i < (long long)cnt;
+    const int q = act ? w.act[dir][i] : 0;
+    y = q / W;
+    x = q - y * W;
+  } else {
+    const long long i = ((long long)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + wave) * NG + g;
+    act = g < NG && i < (long long)Wh * H;
+    y = act ? (int)(i / Wh) : 0;
+    x = act ? 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1) : 0;
+    act = act && x < W;
+  }
   const int p = y * W + x;
-  if (act && restricted) act = w.win[dir][p] < 0;
   unsigned evals = 0, rows = 0;
   if (act) {
     const int label = restricted ? w.hlabel[dir][p] : -1;
@@ -614,6 +661,15 @@ static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int ite
   const long long n = (long long)((P.W + 1) >> 1) * P.H;
   const long long per = (long long)NG * (kBlock / kWave);
   const int nb = (int)((n + per - 1) / per);
+  if (restricted) {
+    hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + kBlock - 1) / kBlock), 2), dim3(kBlock), 0, s, P, w,
+                       colour);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((k_pm_halfsweep<R, C, FP16, IDENT>), dim3(nb, 2), dim3(kBlock), 0, s, P, w, colour, iter, slot,
                      restricted);
   return hipGetLastError();

@@ -45,6 +45,7 @@ class Layout(ctypes.Structure):
         ("nnf", ctypes.c_uint64 * 2), ("cost", ctypes.c_uint64 * 2), ("win", ctypes.c_uint64 * 2),
         ("loss", ctypes.c_uint64 * 2), ("hlabel", ctypes.c_uint64 * 2), ("twin", ctypes.c_uint64 * 2),
         ("tloss", ctypes.c_uint64 * 2), ("planes", ctypes.c_uint64), ("counters", ctypes.c_uint64),
+        ("active", ctypes.c_uint64),
         ("n_planes", ctypes.c_int32), ("n_levels", ctypes.c_int32),
         ("level_blocks", ctypes.c_int32 * MAX_LEVELS), ("level_nbx", ctypes.c_int32 * MAX_LEVELS),
     ]
