@@ -221,56 +221,80 @@ __device__ inline int group_geometry(bool ok, bool integral, int base) {
   return bad != 0.f ? 2 : (frac == 0.f ? 1 : 0);
 }
 
-// Adds the lane's taps of rows [T0, T1) for target (tx, ty) to acc.  Integral
-// geometry: one pixel per tap.  Otherwise bilinear: the corner pairs of the
-// tap's two rows, each one contiguous load.  No branches inside, so the loads
-// of all the rows can be in flight together.
+// Adds the lane's taps of rows [T0, T1) for target (tx, ty) to acc, in row
+// order.  Integral geometry: one pixel per tap.  Otherwise bilinear: the
+// corner pairs of the tap's two rows, each one contiguous load.  Rows are
+// taken three at a time: all their loads are issued first and a scheduling
+// barrier keeps them ahead of the arithmetic, so a wave has the gathers of
+// three rows in flight instead of waiting on each row in turn.
 template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL, int T0, int T1>
 __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H,
                                  int tx, int ty, float gw) {
+  if constexpr (T1 - T0 > 3) {
+    acc = add_rows<R, C, FP16, IDENT, INTEGRAL, T0, T0 + 3>(acc, L, F2, W, H, tx, ty, gw);
+    return add_rows<R, C, FP16, IDENT, INTEGRAL, T0 + 3, T1>(acc, L, F2, W, H, tx, ty, gw);
+  } else if constexpr (IDENT || INTEGRAL) {
+    constexpr int N = T1 - T0;
+    float v[N][C];
 #pragma unroll
-  for (int t = T0; t < T1; ++t) {
-    float v[C];
-    if constexpr (IDENT) {
-      const int bx = clampi(tx + L.dx, 0, W - 1);
-      const int by = clampi(ty + t - R, 0, H - 1);
-      Px<C, FP16>::load1(F2, by * W + bx, v);
-    } else if constexpr (INTEGRAL) {
-      const int bx = clampi(tx + L.ox[t], 0, W - 1);
-      const int by = clampi(ty + L.oy[t], 0, H - 1);
-      Px<C, FP16>::load1(F2, by * W + bx, v);
-    } else {
+    for (int n = 0; n < N; ++n) {
+      const int t = T0 + n;
+      int bx, by;
+      if constexpr (IDENT) {
+        bx = clampi(tx + L.dx, 0, W - 1);
+        by = clampi(ty + t - R, 0, H - 1);
+      } else {
+        bx = clampi(tx + L.ox[t], 0, W - 1);
+        by = clampi(ty + L.oy[t], 0, H - 1);
+      }
+      Px<C, FP16>::load1(F2, by * W + bx, v[n]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int n = 0; n < N; ++n) acc += tap_sq<C>(L.f1[T0 + n], v[n], gw);
+    return acc;
+  } else {
+    constexpr int N = T1 - T0;
+    float a[N][C], b[N][C], c[N][C], d[N][C], fx[N], fy[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const int t = T0 + n;
       int bx = tx + L.ox[t], by = ty + L.oy[t];
-      float fx = L.fx[t], fy = L.fy[t];
+      fx[n] = L.fx[t];
+      fy[n] = L.fy[t];
       if (bx < 0) {
         bx = 0;
-        fx = 0.f;
+        fx[n] = 0.f;
       } else if (bx >= W - 1) {
         bx = W - 1;
-        fx = 0.f;
+        fx[n] = 0.f;
       }
       if (by < 0) {
         by = 0;
-        fy = 0.f;
+        fy[n] = 0.f;
       } else if (by >= H - 1) {
         by = H - 1;
-        fy = 0.f;
+        fy[n] = 0.f;
       }
       const int i0 = by * W + bx;
       const int i1 = i0 + (by < H - 1 ? W : 0);
-      float a[C], b[C], c[C], d[C];
-      Px<C, FP16>::load2(F2, i0, a, b);
-      Px<C, FP16>::load2(F2, i1, c, d);
+      Px<C, FP16>::load2(F2, i0, a[n], b[n]);
+      Px<C, FP16>::load2(F2, i1, c[n], d[n]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      float v[C];
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        const float top = fmaf(fx, b[k] - a[k], a[k]);
-        const float bot = fmaf(fx, d[k] - c[k], c[k]);
-        v[k] = fmaf(fy, bot - top, top);
+        const float top = fmaf(fx[n], b[n][k] - a[n][k], a[n][k]);
+        const float bot = fmaf(fx[n], d[n][k] - c[n][k], c[n][k]);
+        v[k] = fmaf(fy[n], bot - top, top);
       }
+      acc += tap_sq<C>(L.f1[T0 + n], v, gw);
     }
-    acc += tap_sq<C>(L.f1[t], v, gw);
+    return acc;
   }
-  return acc;
 }
 
 // Group cost of target (tx, ty).  With EE the running group sum is compared
@@ -526,7 +550,7 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
 // ---------------------------------------------------------------------------
 // Restricted half-sweeps update only the unassigned pixels of one colour.
 // They are listed first, so that every lane group of the sweep has a pixel:
-// each wave appends its active pixels (row-major within the wave's span) at a
+// each workgroup appends the active pixels of its span (row-major) at a
 // position taken from a counter.  The order of the spans in the list varies
 // between runs; the update of a pixel does not depend on it.
 // ---------------------------------------------------------------------------
@@ -534,25 +558,46 @@ __global__ void k_zero_active(Ws w) {
   if (threadIdx.x < 2) w.act_count[threadIdx.x] = 0u;
 }
 
+constexpr int kListSpan = 4;  // pixels of the colour per thread of k_active_list
+
 __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int colour) {
+  __shared__ int s_cnt[kListSpan * (kBlock / kWave)];
+  __shared__ unsigned s_base;
   const int dir = blockIdx.y;
   const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  bool act = i < (long long)Wh * H;
-  int p = 0;
-  if (act) {
-    const int y = (int)(i / Wh);
-    const int x = 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1);
-    p = y * W + x;
-    act = x < W && w.win[dir][p] < 0;
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  int pix[kListSpan];
+  bool act[kListSpan];
+  unsigned long long m[kListSpan];
+#pragma unroll
+  for (int k = 0; k < kListSpan; ++k) {
+    const long long i = ((long long)blockIdx.x * kListSpan + k) * kBlock + t;
+    act[k] = i < (long long)Wh * H;
+    pix[k] = 0;
+    if (act[k]) {
+      const int y = (int)(i / Wh);
+      const int x = 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1);
+      pix[k] = y * W + x;
+      act[k] = x < W && w.win[dir][pix[k]] < 0;
+    }
+    m[k] = __ballot(act[k]);
+    if (lane == 0) s_cnt[k * (kBlock / kWave) + wave] = __popcll(m[k]);
   }
-  const unsigned long long m = __ballot(act);
-  if (m == 0ull) return;
-  unsigned base = 0u;
-  if (lane == 0) base = atomicAdd(&w.act_count[dir], (unsigned)__popcll(m));
-  base = __shfl(base, 0);
-  if (act) w.act[dir][base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+  __syncthreads();
+  if (t == 0) {
+    unsigned total = 0u;
+    for (int k = 0; k < kListSpan * (kBlock / kWave); ++k) total += s_cnt[k];
+    s_base = total ? atomicAdd(&w.act_count[dir], total) : 0u;
+  }
+  __syncthreads();
+  unsigned pos = s_base;
+  int done = 0;
+#pragma unroll
+  for (int k = 0; k < kListSpan; ++k) {
+    const int mine = k * (kBlock / kWave) + wave;
+    for (; done < mine; ++done) pos += s_cnt[done];
+    if (act[k]) w.act[dir][pos + __popcll(m[k] & ((1ull << lane) - 1ull))] = pix[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -665,8 +710,8 @@ static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int ite
     hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + kBlock - 1) / kBlock), 2), dim3(kBlock), 0, s, P, w,
-                       colour);
+    const long long span = (long long)kListSpan * kBlock;
+    hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
