@@ -103,6 +103,12 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
       !(p->grad_weight >= 0))
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
   if (p->flags & ~MSGPM_FLAG_FP16) return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
+  {
+    // kernels address one frame's features with 32-bit byte offsets
+    const uint64_t px_bytes = (p->flags & MSGPM_FLAG_FP16) ? (p->channels == 3 ? 8 : 12) : 4 * (uint64_t)p->channels;
+    if (((uint64_t)p->width * p->height + 1) * px_bytes > 0x7fffffffull)
+      return fail(MSGPM_E_UNSUPPORTED, "frame %dx%d: features exceed 2 GiB", p->width, p->height);
+  }
 
   DevParams d;
   memset(&d, 0, sizeof d);

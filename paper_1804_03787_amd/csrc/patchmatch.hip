@@ -31,64 +31,77 @@
 
 namespace msgpm {
 
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef float f3u __attribute__((ext_vector_type(3), aligned(4)));
-typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
-typedef uint32_t u4u __attribute__((ext_vector_type(4), aligned(4)));
-typedef uint32_t u3u __attribute__((ext_vector_type(3), aligned(4)));
-typedef uint32_t u2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline float2 h2f(uint32_t u) { return __half22float2(__builtin_bit_cast(__half2, u)); }
+__device__ inline float uf(uint32_t u) { return __uint_as_float(u); }
+
+// Feature buffer of one frame, read through a buffer resource: offsets are
+// 32-bit byte offsets (the host rejects frames whose features exceed 2 GiB), so
+// an address costs one integer multiply-add instead of 64-bit arithmetic.
+struct Feat {
+  __amdgpu_buffer_rsrc_t r;
+};
+template <int C, bool FP16>
+__device__ inline Feat feat_buf(const void* F, int W, int H) {
+  constexpr int kBytes = FP16 ? (C == 3 ? 8 : 12) : 4 * C;
+  // word 3 = 0x00020000: 32-bit data format, as raw dword buffer loads need on gfx9
+  return Feat{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(F), (short)0, (W * H + 1) * kBytes, 0x00020000)};
+}
 
 // Feature access.  FP32: C floats per pixel; FP16: C=3 -> 4 halves, C=5 -> 6
 // halves per pixel.  load1 reads pixel idx, load2 pixels idx and idx + 1 with
 // one contiguous access (the buffer is padded so idx + 1 always exists).
 template <int C, bool FP16>
 struct Px {
-  static __device__ inline void load1(const void* __restrict__ F, int idx, float* v) {
+  static constexpr int kBytes = FP16 ? (C == 3 ? 8 : 12) : 4 * C;
+  static __device__ inline void load1(Feat F, int idx, float* v) {
+    const int o = idx * kBytes;
     if constexpr (!FP16) {
-      const float* p = reinterpret_cast<const float*>(F) + (size_t)C * idx;
       if constexpr (C == 3) {
-        const f3u a = *reinterpret_cast<const f3u*>(p);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z;
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(F.r, o, 0, 0);
+        v[0] = uf(a.x); v[1] = uf(a.y); v[2] = uf(a.z);
       } else {
-        const f4u a = *reinterpret_cast<const f4u*>(p);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = p[4];
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+        const uint32_t e = __builtin_amdgcn_raw_buffer_load_b32(F.r, o + 16, 0, 0);
+        v[0] = uf(a.x); v[1] = uf(a.y); v[2] = uf(a.z); v[3] = uf(a.w); v[4] = uf(e);
       }
     } else {
       if constexpr (C == 3) {
-        const u2u u = *reinterpret_cast<const u2u*>(reinterpret_cast<const uint16_t*>(F) + 4 * (size_t)idx);
+        const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(F.r, o, 0, 0);
         const float2 a = h2f(u.x), b = h2f(u.y);
         v[0] = a.x; v[1] = a.y; v[2] = b.x;
       } else {
-        const u3u u = *reinterpret_cast<const u3u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx);
+        const u32x3 u = __builtin_amdgcn_raw_buffer_load_b96(F.r, o, 0, 0);
         const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z);
         v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x;
       }
     }
   }
-  static __device__ inline void load2(const void* __restrict__ F, int idx, float* v, float* w) {
+  static __device__ inline void load2(Feat F, int idx, float* v, float* w) {
+    const int o = idx * kBytes;
     if constexpr (!FP16) {
-      const float* p = reinterpret_cast<const float*>(F) + (size_t)C * idx;
       if constexpr (C == 3) {
-        const f4u a = *reinterpret_cast<const f4u*>(p);
-        const f2u b = *reinterpret_cast<const f2u*>(p + 4);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; w[0] = a.w; w[1] = b.x; w[2] = b.y;
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(F.r, o + 16, 0, 0);
+        v[0] = uf(a.x); v[1] = uf(a.y); v[2] = uf(a.z); w[0] = uf(a.w); w[1] = uf(b.x); w[2] = uf(b.y);
       } else {
-        const f4u a = *reinterpret_cast<const f4u*>(p);
-        const f4u b = *reinterpret_cast<const f4u*>(p + 4);
-        const f2u c = *reinterpret_cast<const f2u*>(p + 8);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x;
-        w[0] = b.y; w[1] = b.z; w[2] = b.w; w[3] = c.x; w[4] = c.y;
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(F.r, o + 16, 0, 0);
+        const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(F.r, o + 32, 0, 0);
+        v[0] = uf(a.x); v[1] = uf(a.y); v[2] = uf(a.z); v[3] = uf(a.w); v[4] = uf(b.x);
+        w[0] = uf(b.y); w[1] = uf(b.z); w[2] = uf(b.w); w[3] = uf(c.x); w[4] = uf(c.y);
       }
     } else {
       if constexpr (C == 3) {
-        const u4u u = *reinterpret_cast<const u4u*>(reinterpret_cast<const uint16_t*>(F) + 4 * (size_t)idx);
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
         const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z), d = h2f(u.w);
         v[0] = a.x; v[1] = a.y; v[2] = b.x; w[0] = c.x; w[1] = c.y; w[2] = d.x;
       } else {
-        const u4u u = *reinterpret_cast<const u4u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx);
-        const u2u t = *reinterpret_cast<const u2u*>(reinterpret_cast<const uint16_t*>(F) + 6 * (size_t)idx + 8);
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+        const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(F.r, o + 16, 0, 0);
         const float2 a = h2f(u.x), b = h2f(u.y), c = h2f(u.z), d = h2f(u.w), e = h2f(t.x), f = h2f(t.y);
         v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x;
         w[0] = d.x; w[1] = d.y; w[2] = e.x; w[3] = e.y; w[4] = f.x;
@@ -106,7 +119,9 @@ struct LaneCol {
   static constexpr int TG = IDENT ? 1 : T;
   float f1[T][C];
   int dx;
-  int ox[TG], oy[TG];
+  int o[TG];  // integer part of Delta: x in the low, y in the high 16 bits
+  __device__ int ox(int t) const { return (int)(short)(o[t] & 0xffff); }
+  __device__ int oy(int t) const { return o[t] >> 16; }
   float fx[TG], fy[TG];
 };
 
@@ -124,8 +139,7 @@ __device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, 
     if (H == nullptr) {
 #pragma unroll
       for (int t = 0; t < 2 * R + 1; ++t) {
-        L.ox[t] = dx;
-        L.oy[t] = t - R;
+        L.o[t] = pack_off(dx, t - R);
         L.fx[t] = 0.f;
         L.fy[t] = 0.f;
       }
@@ -153,8 +167,9 @@ __device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, 
       Dx = fminf(fmaxf(Dx, -lim), lim);
       Dy = fminf(fmaxf(Dy, -lim), lim);
       const float flx = floorf(Dx), fly = floorf(Dy);
-      L.ox[t] = (int)flx;
-      L.oy[t] = (int)fly;
+      // integer parts beyond +-32767 (frames are at most 32767 pixels) select
+      // the same clamped border pixel with fraction 0, so they are cut there
+      L.o[t] = pack_off((int)fminf(fmaxf(flx, -32767.f), 32767.f), (int)fminf(fmaxf(fly, -32767.f), 32767.f));
       L.fx[t] = Dx - flx;
       L.fy[t] = Dy - fly;
       integral = integral && (L.fx[t] == 0.f) && (L.fy[t] == 0.f);
@@ -164,7 +179,7 @@ __device__ inline bool setup_geometry(LaneCol<R, C, IDENT>& L, const double* H, 
 }
 
 template <int R, int C, bool FP16, bool IDENT>
-__device__ inline void load_column(LaneCol<R, C, IDENT>& L, const void* F1, int W, int H, int x, int y, int dx) {
+__device__ inline void load_column(LaneCol<R, C, IDENT>& L, Feat F1, int W, int H, int x, int y, int dx) {
   const int cx = clampi(x + dx, 0, W - 1);
 #pragma unroll
   for (int t = 0; t < 2 * R + 1; ++t) {
@@ -184,13 +199,21 @@ __device__ inline float tap_sq(const float* f1, const float* v, float gw) {
   return row;
 }
 
-// Sum of the group's column partials in lane order; identical on every lane.
+// Sum of the group's column partials in lane order, identical on every lane
+// of the group.  Eight adds with the wave shifted right by one lane leave at
+// lane l the sum ((v[l-G+1] + v[l-G+2]) + ...) + v[l]; at the group's last lane
+// that is its G partials in lane order, which is then broadcast.  Groups never
+// straddle inactive lanes: a group is active or inactive as a whole.
 template <int G>
 __device__ inline float group_sum(float v, int base) {
-  float s = 0.f;
+  float s = v;
 #pragma unroll
-  for (int k = 0; k < G; ++k) s += __shfl(v, base + k);
-  return s;
+  for (int k = 1; k < G; ++k) {
+    const float sh =
+        __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x138, 0xf, 0xf, false));
+    s = sh + v;
+  }
+  return __shfl(s, base + G - 1);
 }
 
 __device__ inline const double* plane_H(const Ws& w, int label) {
@@ -228,7 +251,7 @@ __device__ inline int group_geometry(bool ok, bool integral, int base) {
 // barrier keeps them ahead of the arithmetic, so a wave has the gathers of
 // three rows in flight instead of waiting on each row in turn.
 template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL, int T0, int T1>
-__device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H,
+__device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat F2, int W, int H,
                                  int tx, int ty, float gw) {
   if constexpr (T1 - T0 > 3) {
     acc = add_rows<R, C, FP16, IDENT, INTEGRAL, T0, T0 + 3>(acc, L, F2, W, H, tx, ty, gw);
@@ -244,8 +267,8 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const
         bx = clampi(tx + L.dx, 0, W - 1);
         by = clampi(ty + t - R, 0, H - 1);
       } else {
-        bx = clampi(tx + L.ox[t], 0, W - 1);
-        by = clampi(ty + L.oy[t], 0, H - 1);
+        bx = clampi(tx + L.ox(t), 0, W - 1);
+        by = clampi(ty + L.oy(t), 0, H - 1);
       }
       Px<C, FP16>::load1(F2, by * W + bx, v[n]);
     }
@@ -259,23 +282,12 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const int t = T0 + n;
-      int bx = tx + L.ox[t], by = ty + L.oy[t];
-      fx[n] = L.fx[t];
-      fy[n] = L.fy[t];
-      if (bx < 0) {
-        bx = 0;
-        fx[n] = 0.f;
-      } else if (bx >= W - 1) {
-        bx = W - 1;
-        fx[n] = 0.f;
-      }
-      if (by < 0) {
-        by = 0;
-        fy[n] = 0.f;
-      } else if (by >= H - 1) {
-        by = H - 1;
-        fy[n] = 0.f;
-      }
+      // base pixel clamped into the frame; a fraction survives only where the
+      // base and its right (lower) neighbour are both inside
+      const int ux = tx + L.ox(t), uy = ty + L.oy(t);
+      const int bx = min(max(ux, 0), W - 1), by = min(max(uy, 0), H - 1);
+      fx[n] = (unsigned)ux < (unsigned)(W - 1) ? L.fx[t] : 0.f;
+      fy[n] = (unsigned)uy < (unsigned)(H - 1) ? L.fy[t] : 0.f;
       const int i0 = by * W + bx;
       const int i1 = i0 + (by < H - 1 ? W : 0);
       Px<C, FP16>::load2(F2, i0, a[n], b[n]);
@@ -284,13 +296,11 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int n = 0; n < N; ++n) {
+      const float gx = 1.f - fx[n], gy = 1.f - fy[n];
+      const float w00 = gx * gy, w01 = fx[n] * gy, w10 = gx * fy[n], w11 = fx[n] * fy[n];
       float v[C];
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        const float top = fmaf(fx[n], b[n][k] - a[n][k], a[n][k]);
-        const float bot = fmaf(fx[n], d[n][k] - c[n][k], c[n][k]);
-        v[k] = fmaf(fy[n], bot - top, top);
-      }
+      for (int k = 0; k < C; ++k) v[k] = fmaf(w11, d[n][k], fmaf(w10, c[n][k], fmaf(w01, b[n][k], w00 * a[n][k])));
       acc += tap_sq<C>(L.f1[T0 + n], v, gw);
     }
     return acc;
@@ -305,7 +315,7 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, const
 // candidate is summed in the same order as without the checks.  rows returns
 // the tap rows computed.
 template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL, bool EE>
-__device__ inline float group_cost(const LaneCol<R, C, IDENT>& L, const void* __restrict__ F2, int W, int H, int tx,
+__device__ inline float group_cost(const LaneCol<R, C, IDENT>& L, Feat F2, int W, int H, int tx,
                                    int ty, float gw, int base, float bound, bool& rejected, unsigned& rows) {
   constexpr int T = 2 * R + 1, T1 = T / 3, T2 = (2 * T) / 3;
   rejected = false;
@@ -358,15 +368,15 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
     const int32_t v = w.nnf[dir][p];
     float c = __builtin_huge_valf();
     if (geo != 2) {
-      load_column<R, C, FP16, IDENT>(L, w.feat[dir], W, H, x, y, j - R);
+      load_column<R, C, FP16, IDENT>(L, feat_buf<C, FP16>(w.feat[dir], W, H), W, H, x, y, j - R);
       const int tx = x + off_dx(v), ty = y + off_dy(v);
       bool rejected;
       unsigned rows = 0;
       if (IDENT || geo == 1)
-        c = group_cost<R, C, FP16, IDENT, true, false>(L, w.feat[1 - dir], W, H, tx, ty, P.gw, base, 0.f, rejected,
+        c = group_cost<R, C, FP16, IDENT, true, false>(L, feat_buf<C, FP16>(w.feat[1 - dir], W, H), W, H, tx, ty, P.gw, base, 0.f, rejected,
                                                        rows);
       else
-        c = group_cost<R, C, FP16, IDENT, IDENT, false>(L, w.feat[1 - dir], W, H, tx, ty, P.gw, base, 0.f, rejected,
+        c = group_cost<R, C, FP16, IDENT, IDENT, false>(L, feat_buf<C, FP16>(w.feat[1 - dir], W, H), W, H, tx, ty, P.gw, base, 0.f, rejected,
                                                         rows);
     }
     if (j == 0) {
@@ -391,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
 // issuing the loads of all NB candidates per tap; every candidate is summed in
 // the same order as a lone evaluation.
 template <int R, int C, bool FP16, int NB>
-__device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, const void* __restrict__ F2, int W,
+__device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
                                               int H, const int* tx, const int* ty, float gw, int base, float* cost) {
   constexpr int T = 2 * R + 1;
   float acc[NB];
@@ -413,7 +423,7 @@ __device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, cons
 }
 
 template <int R, int C, bool FP16, int NB>
-__device__ inline void ident_batch(const LaneCol<R, C, true>& L, const void* F2, int W, int H, const int* tx,
+__device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                    const int* ty, const bool* ok, float gw, int base, int& btx, int& bty, float& bc,
                                    unsigned& evals) {
   bool any = false;
@@ -441,7 +451,7 @@ __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const D
                                            unsigned& rows) {
   constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G, NB = 4;
   const int W = P.W, H = P.H, p = y * W + x;
-  const void* F2 = w.feat[1 - dir];
+  const Feat F2 = feat_buf<C, FP16>(w.feat[1 - dir], W, H);
   const int32_t* nnf = w.nnf[dir];
   const int32_t v0 = nnf[p];
   int btx = x + off_dx(v0), bty = y + off_dy(v0);
@@ -496,7 +506,7 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
   constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G;
   constexpr bool EE = true;
   const int W = P.W, H = P.H, p = y * W + x;
-  const void* F2 = w.feat[1 - dir];
+  const Feat F2 = feat_buf<C, FP16>(w.feat[1 - dir], W, H);
   const int32_t* nnf = w.nnf[dir];
   const int32_t v0 = nnf[p];
   int btx = x + off_dx(v0), bty = y + off_dy(v0);
@@ -604,8 +614,10 @@ __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int c
 // One red-black half-sweep over the pixels of one colour, both directions
 // (restricted: over the listed pixels).
 // ---------------------------------------------------------------------------
+// The distorted-patch form is held to 168 VGPRs (3 waves per SIMD): on MI355X
+// the extra wave hides more gather latency than the few registers it costs.
 template <int R, int C, bool FP16, bool IDENT>
-__global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int colour, int iter, int slot,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void k_pm_halfsweep(DevParams P, Ws w, int colour, int iter, int slot,
                                                         int restricted) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -663,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_pm_halfsweep(DevParams P, Ws w, int 
     const int geo = group_geometry<G>(ok, integral, base);
     // a non-positive homogeneous coordinate makes every candidate +inf: no update
     if (geo != 2) {
-      load_column<R, C, FP16, IDENT>(L, w.feat[dir], W, H, x, y, j - R);
+      load_column<R, C, FP16, IDENT>(L, feat_buf<C, FP16>(w.feat[dir], W, H), W, H, x, y, j - R);
       // plane candidate: where the region plane sends p, rounded to the grid
       bool has_plane = false;
       int ptx = 0, pty = 0;
