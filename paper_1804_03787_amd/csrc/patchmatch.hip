@@ -400,6 +400,11 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
 // Group costs of NB identity-patch targets: each lane walks its column once,
 // issuing the loads of all NB candidates per tap; every candidate is summed in
 // the same order as a lone evaluation.
+#ifndef MSGPM_IDENT_ROWS
+#define MSGPM_IDENT_ROWS 1
+#endif
+constexpr int kIdentRows = MSGPM_IDENT_ROWS;  // tap rows per load chunk of identity-patch batches
+
 template <int R, int C, bool FP16, int NB>
 __device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
                                               int H, const int* tx, const int* ty, float gw, int base, float* cost) {
@@ -407,16 +412,29 @@ __device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat
   float acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+  // rows in chunks of kIdentRows: the loads of a chunk (all candidates) are
+  // issued ahead of its arithmetic
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
+  for (int t0 = 0; t0 < T; t0 += kIdentRows) {
+    constexpr int TC = kIdentRows;
+    float v[TC][NB][C];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      float v[C];
-      const int bx = clampi(tx[b] + L.dx, 0, W - 1);
-      const int by = clampi(ty[b] + t - R, 0, H - 1);
-      Px<C, FP16>::load1(F2, by * W + bx, v);
-      acc[b] += tap_sq<C>(L.f1[t], v, gw);
-    }
+    for (int u = 0; u < TC; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (t0 + u < T) {
+          const int bx = clampi(tx[b] + L.dx, 0, W - 1);
+          const int by = clampi(ty[b] + t0 + u - R, 0, H - 1);
+          Px<C, FP16>::load1(F2, by * W + bx, v[u][b]);
+        }
+      }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < TC; ++u)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (t0 + u < T) acc[b] += tap_sq<C>(L.f1[t0 + u], v[u][b], gw);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) cost[b] = group_sum<T>(acc[b], base);
