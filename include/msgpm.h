@@ -105,9 +105,10 @@ typedef struct msgpm_layout {
   uint64_t tloss[2];       /* double: its loss (scratch) */
   uint64_t planes;         /* msgpm_plane[n_planes] */
   uint64_t counters;       /* uint64[16][64]: evaluation counters, see below */
-  uint64_t active;         /* scratch of restricted half-sweeps: per direction an int32 list of
-                              the pixels to update (ceil(width/2)*height entries, each list
-                              256-byte aligned), then 2 uint32 counts */
+  uint64_t active;         /* scratch of restricted half-sweeps: per direction an int32 buffer
+                              of ceil(width/2)*height entries (256-byte aligned) listing the
+                              pixels to update, those with a region plane from the front,
+                              the others from the back; then 4 uint32 list lengths */
   int32_t n_planes;
   int32_t n_levels;
   int32_t level_blocks[MSGPM_MAX_LEVELS]; /* windows per level and stage */

@@ -43,7 +43,7 @@ struct Ws {
   msgpm_plane* planes;
   unsigned long long* counters;
   int32_t* act[2];        // pixels a restricted half-sweep updates, per direction
-  unsigned* act_count;    // their counts [2]
+  unsigned* act_count;    // list lengths [direction][with region plane, without]
 };
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }

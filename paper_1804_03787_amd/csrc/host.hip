@@ -175,7 +175,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     o.counters = cur;
     cur = align256(cur + (uint64_t)kCounterKinds * kCounterStripes * sizeof(uint64_t));
     o.active = cur;
-    cur = align256(cur + 2 * active_list_bytes(d) + 2 * sizeof(uint32_t));
+    cur = align256(cur + 2 * active_list_bytes(d) + 4 * sizeof(uint32_t));
     o.total_bytes = cur;
     o.n_levels = d.n_levels;
     for (int l = 0; l < d.n_levels; ++l) {

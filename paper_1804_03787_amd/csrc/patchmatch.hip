@@ -577,54 +577,72 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
 
 // ---------------------------------------------------------------------------
 // Restricted half-sweeps update only the unassigned pixels of one colour.
-// They are listed first, so that every lane group of the sweep has a pixel:
-// each workgroup appends the active pixels of its span (row-major) at a
-// position taken from a counter.  The order of the spans in the list varies
-// between runs; the update of a pixel does not depend on it.
+// They are listed first, so that every lane group of the sweep has a pixel,
+// in two lists sharing one buffer per direction: pixels with a region plane
+// from the front (distorted patches), pixels without one from the back
+// (identity patches: the update of the initial pass, without a plane
+// candidate).  Each workgroup appends the pixels of its span (row-major) at
+// positions taken from the two counters; the order of the spans varies between
+// runs, and the update of a pixel does not depend on it.
 // ---------------------------------------------------------------------------
 __global__ void k_zero_active(Ws w) {
-  if (threadIdx.x < 2) w.act_count[threadIdx.x] = 0u;
+  if (threadIdx.x < 4) w.act_count[threadIdx.x] = 0u;
 }
 
 constexpr int kListSpan = 4;  // pixels of the colour per thread of k_active_list
 
 __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int colour) {
-  __shared__ int s_cnt[kListSpan * (kBlock / kWave)];
-  __shared__ unsigned s_base;
+  constexpr int NS = kListSpan * (kBlock / kWave);
+  __shared__ int s_cnt[2][NS];
+  __shared__ unsigned s_base[2];
   const int dir = blockIdx.y;
   const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
+  const unsigned cap = (unsigned)Wh * (unsigned)H;
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
   int pix[kListSpan];
-  bool act[kListSpan];
-  unsigned long long m[kListSpan];
+  bool inA[kListSpan], inB[kListSpan];
+  unsigned long long mA[kListSpan], mB[kListSpan];
 #pragma unroll
   for (int k = 0; k < kListSpan; ++k) {
     const long long i = ((long long)blockIdx.x * kListSpan + k) * kBlock + t;
-    act[k] = i < (long long)Wh * H;
+    bool act = i < (long long)cap;
     pix[k] = 0;
-    if (act[k]) {
+    bool plane = false;
+    if (act) {
       const int y = (int)(i / Wh);
       const int x = 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1);
       pix[k] = y * W + x;
-      act[k] = x < W && w.win[dir][pix[k]] < 0;
+      act = x < W && w.win[dir][pix[k]] < 0;
+      plane = act && w.hlabel[dir][pix[k]] >= 0;
     }
-    m[k] = __ballot(act[k]);
-    if (lane == 0) s_cnt[k * (kBlock / kWave) + wave] = __popcll(m[k]);
+    inA[k] = plane;
+    inB[k] = act && !plane;
+    mA[k] = __ballot(inA[k]);
+    mB[k] = __ballot(inB[k]);
+    if (lane == 0) {
+      s_cnt[0][k * (kBlock / kWave) + wave] = __popcll(mA[k]);
+      s_cnt[1][k * (kBlock / kWave) + wave] = __popcll(mB[k]);
+    }
   }
   __syncthreads();
-  if (t == 0) {
+  if (t < 2) {
     unsigned total = 0u;
-    for (int k = 0; k < kListSpan * (kBlock / kWave); ++k) total += s_cnt[k];
-    s_base = total ? atomicAdd(&w.act_count[dir], total) : 0u;
+    for (int k = 0; k < NS; ++k) total += s_cnt[t][k];
+    s_base[t] = total ? atomicAdd(&w.act_count[2 * dir + t], total) : 0u;
   }
   __syncthreads();
-  unsigned pos = s_base;
+  unsigned posA = s_base[0], posB = s_base[1];
   int done = 0;
+  const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int k = 0; k < kListSpan; ++k) {
     const int mine = k * (kBlock / kWave) + wave;
-    for (; done < mine; ++done) pos += s_cnt[done];
-    if (act[k]) w.act[dir][pos + __popcll(m[k] & ((1ull << lane) - 1ull))] = pix[k];
+    for (; done < mine; ++done) {
+      posA += s_cnt[0][done];
+      posB += s_cnt[1][done];
+    }
+    if (inA[k]) w.act[dir][posA + __popcll(mA[k] & lt)] = pix[k];
+    if (inB[k]) w.act[dir][cap - 1u - (posB + __popcll(mB[k] & lt))] = pix[k];
   }
 }
 
@@ -645,14 +663,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
   bool act;
   int x, y;
   if (restricted) {
-    // only the workgroups covering the list work; each XCD takes a contiguous part
-    const unsigned cnt = w.act_count[dir];
+    // only the workgroups covering the list work; each XCD takes a contiguous
+    // part.  Distorted patches: the front list; identity patches: the back one.
+    const unsigned cnt = w.act_count[2 * dir + (IDENT ? 1 : 0)];
     constexpr unsigned per = NG * (kBlock / kWave);
     const int nb = (int)((cnt + per - 1) / per);
     if ((int)blockIdx.x >= nb) return;
     const long long i = ((long long)xcd_remap(blockIdx.x, nb) * (kBlock / kWave) + wave) * NG + g;
     act = g < NG && i < (long long)cnt;
-    const int q = act ? w.act[dir][i] : 0;
+    const unsigned cap = (unsigned)Wh * (unsigned)H;
+    const int q = act ? w.act[dir][IDENT ? cap - 1u - (unsigned)i : (unsigned)i] : 0;
     y = q / W;
     x = q - y * W;
   } else {
@@ -736,18 +756,28 @@ static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int ite
   const long long n = (long long)((P.W + 1) >> 1) * P.H;
   const long long per = (long long)NG * (kBlock / kWave);
   const int nb = (int)((n + per - 1) / per);
-  if (restricted) {
-    hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const long long span = (long long)kListSpan * kBlock;
-    hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL((k_pm_halfsweep<R, C, FP16, IDENT>), dim3(nb, 2), dim3(kBlock), 0, s, P, w, colour, iter, slot,
                      restricted);
   return hipGetLastError();
+}
+
+// Restricted half-sweep: list the pixels, then the distorted-patch kernel over
+// the front list and the identity-patch kernel over the back one (both read
+// only the other colour, so their order does not matter).
+template <int R, int C, bool FP16>
+static hipError_t pm_restricted_launch(const DevParams& P, const Ws& w, int colour, int iter, int slot,
+                                       hipStream_t s) {
+  const long long n = (long long)((P.W + 1) >> 1) * P.H;
+  hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long span = (long long)kListSpan * kBlock;
+  hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, 1, s);
+  if (e != hipSuccess) return e;
+  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 1, s);
 }
 
 template <int R, int C, bool FP16, bool IDENT>
@@ -763,8 +793,8 @@ static hipError_t ec_launch(const DevParams& P, const Ws& w, int mode, hipStream
 template <int R, int C, bool FP16>
 static hipError_t dispatch_pm(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
                               hipStream_t s) {
-  if (restricted) return pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, restricted, s);
-  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, restricted, s);
+  if (restricted) return pm_restricted_launch<R, C, FP16>(P, w, colour, iter, slot, s);
+  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 0, s);
 }
 
 template <int R, int C, bool FP16>
