@@ -32,6 +32,16 @@ W, H = 1024, 436
 PARAMS = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0, seed=0)
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 
+# HBM bytes per launch of each PatchMatch kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and 1.0: what the
+# counters read for a plain 256 MiB copy), averaged over the launches of one
+# pipeline run; None when not measured for the kernels as they are now.
+TRAFFIC = {
+    # profiles/k_pm_halfsweep_1024x436_traffic.md
+    "k_pm_halfsweep (identity patches)": 1.548e9,
+    "k_pm_halfsweep (distorted patches)": 3.499e8,
+}
+
 
 def flops_per_eval(kind: str, r: int, C: int) -> int:
     """Algorithmic FP32 flops of one patch-cost evaluation (FMA = 2).
@@ -114,24 +124,33 @@ def main() -> int:
     # a candidate rejected early by its partial sum counts for the rows it computed
     cnt = g.counters()
     taps_rows = 2 * PARAMS["r"] + 1
-    ev_init = sum(cnt["pm_init"])
-    ev_restr = sum(cnt["pm_restricted"])
-    full_init = sum(cnt["pm_init_rows"]) / taps_rows
-    full_restr = sum(cnt["pm_restricted_rows"]) / taps_rows
+    ev = {k: sum(cnt[k]) for k in ("pm_init", "pm_restricted", "pm_restricted_ident", "eval_cost")}
+    full = {k: sum(cnt[k + "_rows"]) / taps_rows for k in ("pm_init", "pm_restricted", "pm_restricted_ident")}
     occ0 = occs[0].float().mean().item()
     kernel_ms = {k: v[0] / args.steps for k, v in timing.items()}
     launches = {k: v[1] / args.steps for k, v in timing.items()}
-    dominant = max(kernel_ms, key=kernel_ms.get)
     r, C = params["r"], params["C"]
-    work = {"pm_init": full_init * flops_per_eval("identity", r, C),
-            "pm_restricted": full_restr * flops_per_eval("warped", r, C)}
+    # the two PatchMatch kernels: identity patches (initial pass and restricted
+    # pixels without a region plane) and distorted patches (restricted pixels with one)
+    kernels = {
+        "k_pm_halfsweep (identity patches)": (
+            kernel_ms["pm_init"] + kernel_ms["pm_restricted_ident"],
+            launches["pm_init"] + launches["pm_restricted_ident"],
+            (full["pm_init"] + full["pm_restricted_ident"]) * flops_per_eval("identity", r, C)),
+        "k_pm_halfsweep (distorted patches)": (
+            kernel_ms["pm_restricted"], launches["pm_restricted"],
+            full["pm_restricted"] * flops_per_eval("warped", r, C)),
+    }
+    dominant = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_launches, dom_flops = kernels[dominant]
     roofline = None
-    if dominant in work and kernel_ms[dominant] > 0:
-        achieved = work[dominant] / (kernel_ms[dominant] * 1e-3) / 1e12
+    if dom_ms > 0:
+        achieved = dom_flops / (dom_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                    "kernel": "k_pm_halfsweep (" + ("identity" if dominant == "pm_init" else "warped") + " patches)",
-                    "avg_launch_us": round(kernel_ms[dominant] * 1e3 / max(launches[dominant], 1), 2)}
+                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": TRAFFIC.get(dominant),
+                    "traffic_unit": "bytes per launch",
+                    "kernel": dominant, "ms_per_step": round(dom_ms, 3),
+                    "avg_launch_us": round(dom_ms * 1e3 / max(dom_launches, 1), 2)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,9 +173,9 @@ def main() -> int:
         "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
                                "8 PM iterations, 256 RANSAC hypotheses",
                    "width": W, "height": H, "seed": 0, "fp16_storage": bool(args.fp16)},
-        "warped_patch_evals_per_s": round((ev_init + ev_restr) / (ms_per_step * 1e-3), 1),
-        "evals_per_step": {"pm_init": ev_init, "pm_restricted": ev_restr, "eval_cost": sum(cnt["eval_cost"]),
-                           "pm_init_full_equiv": round(full_init), "pm_restricted_full_equiv": round(full_restr)},
+        "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
+                                   / (ms_per_step * 1e-3), 1),
+        "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in kernel_ms.items()},
         "occluded_fraction_dir0": round(occ0, 4),
         "roofline": roofline,

@@ -215,14 +215,16 @@ enum {
   MSGPM_T_INIT = 1,
   MSGPM_T_EVAL_COST = 2,
   MSGPM_T_PM_INIT = 3,       /* PatchMatch half-sweeps of the initial pass (identity patches) */
-  MSGPM_T_PM_RESTRICTED = 4, /* PatchMatch half-sweeps restricted to unassigned pixels (warped patches) */
+  MSGPM_T_PM_RESTRICTED = 4, /* restricted half-sweeps, pixels with a region plane (distorted patches) */
   MSGPM_T_RANSAC = 5,
   MSGPM_T_ASSIGN = 6,
   MSGPM_T_SYMMETRY = 7,
   MSGPM_T_FB = 8,
   MSGPM_T_NNF_UPDATE = 9,
   MSGPM_T_FINALIZE = 10,
-  MSGPM_TIMER_KINDS = 11
+  MSGPM_T_PM_LIST = 11,            /* pixel lists of the restricted half-sweeps */
+  MSGPM_T_PM_RESTRICTED_IDENT = 12, /* restricted half-sweeps, pixels without one (identity patches) */
+  MSGPM_TIMER_KINDS = 13
 };
 msgpm_status msgpm_timing_enable(int on);
 msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
@@ -231,10 +233,11 @@ msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
    each kept as 64 partial sums to be added by the reader), per direction
    d = 0, 1, reset by msgpm_init_state:
      [0 + d] candidates evaluated by the initial PatchMatch pass,
-     [2 + d] cost refreshes, [4 + d] candidates of the restricted passes,
-     [6 + d], [8 + d] patch rows (2r+1 taps each) actually computed by the
-     initial and restricted passes (a candidate rejected early by its partial
-     sum computes fewer rows). */
+     [2 + d] cost refreshes, [4 + d] candidates of the restricted passes at
+     pixels with a region plane, [10 + d] at pixels without one,
+     [6 + d], [8 + d], [12 + d] patch rows (2r+1 taps each) actually computed
+     by the initial pass and the two restricted kinds (a candidate rejected
+     early by its partial sum computes fewer rows). */
 
 #ifdef __cplusplus
 }

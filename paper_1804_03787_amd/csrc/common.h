@@ -122,8 +122,13 @@ hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hip
 hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
                              hipStream_t s);
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s);
+// initial pass (identity patches over every pixel of the colour)
 hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
                                hipStream_t s);
+// restricted pass: the pixel lists, then one kernel per list
+hipError_t launch_pm_list(const DevParams& P, const Ws& w, int colour, hipStream_t s);
+hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
+                                hipStream_t s);
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
 hipError_t launch_assign(const DevParams& P, const Ws& w, int level, int stage, int tentative, hipStream_t s);
 hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);

@@ -232,10 +232,20 @@ msgpm_status check_level(const Ctx& c, int level, int stage) {
   return MSGPM_OK;
 }
 
+msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted) {
+  if (!restricted)
+    return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_halfsweep");
+  msgpm_status st = check(timed(MSGPM_T_PM_LIST, c.s, [&] { return launch_pm_list(c.P, c.w, colour, c.s); }), "pm_list");
+  if (st != MSGPM_OK) return st;
+  st = check(timed(MSGPM_T_PM_RESTRICTED, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_restricted");
+  if (st != MSGPM_OK) return st;
+  return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, c.s); }), "pm_restricted");
+}
+
 msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
   for (int it = 0; it < c.P.iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      msgpm_status st = check(timed(restricted ? MSGPM_T_PM_RESTRICTED : MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, restricted, c.s); }), "pm_halfsweep");
+      msgpm_status st = run_halfsweep(c, colour, it, slot, restricted);
       if (st != MSGPM_OK) return st;
     }
   return MSGPM_OK;
@@ -286,7 +296,7 @@ msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, i
   if (st != MSGPM_OK) return st;
   if (colour != 0 && colour != 1) return fail(MSGPM_E_INVALID, "colour must be 0 or 1");
   if (iter < 0 || slot < 0 || slot > 255) return fail(MSGPM_E_INVALID, "iter or slot out of range");
-  return check(timed(restricted ? MSGPM_T_PM_RESTRICTED : MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, iter, slot, restricted ? 1 : 0, c.s); }), "pm_halfsweep");
+  return run_halfsweep(c, colour, iter, slot, restricted ? 1 : 0);
 }
 
 msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {

@@ -742,8 +742,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
     }
     if (j != 0) evals = rows = 0;
   }
-  count_evals<IDENT>(w.counters, (restricted ? 4 : 0) + dir, evals);
-  count_evals<IDENT>(w.counters, (restricted ? 8 : 6) + dir, rows);
+  count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 10 : 4) : 0) + dir, evals);
+  count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 12 : 8) : 6) + dir, rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -761,23 +761,25 @@ static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int ite
   return hipGetLastError();
 }
 
-// Restricted half-sweep: list the pixels, then the distorted-patch kernel over
-// the front list and the identity-patch kernel over the back one (both read
-// only the other colour, so their order does not matter).
+// Restricted half-sweep: list the pixels (launch_pm_list), then the
+// distorted-patch kernel over the front list and the identity-patch kernel over
+// the back one (both read only the other colour, so their order does not
+// matter).
 template <int R, int C, bool FP16>
-static hipError_t pm_restricted_launch(const DevParams& P, const Ws& w, int colour, int iter, int slot,
-                                       hipStream_t s) {
+static hipError_t dispatch_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
+                                      hipStream_t s) {
+  if (ident) return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 1, s);
+  return pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, 1, s);
+}
+
+hipError_t launch_pm_list(const DevParams& P, const Ws& w, int colour, hipStream_t s) {
   const long long n = (long long)((P.W + 1) >> 1) * P.H;
   hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long span = (long long)kListSpan * kBlock;
   hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, 1, s);
-  if (e != hipSuccess) return e;
-  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 1, s);
+  return hipGetLastError();
 }
 
 template <int R, int C, bool FP16, bool IDENT>
@@ -793,7 +795,7 @@ static hipError_t ec_launch(const DevParams& P, const Ws& w, int mode, hipStream
 template <int R, int C, bool FP16>
 static hipError_t dispatch_pm(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
                               hipStream_t s) {
-  if (restricted) return pm_restricted_launch<R, C, FP16>(P, w, colour, iter, slot, s);
+  (void)restricted;
   return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 0, s);
 }
 
@@ -822,6 +824,11 @@ static hipError_t dispatch_ec(const DevParams& P, const Ws& w, int mode, hipStre
 hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
                                hipStream_t s) {
   MSGPM_DISPATCH(dispatch_pm, P, w, colour, iter, slot, restricted, s);
+}
+
+hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
+                                hipStream_t s) {
+  MSGPM_DISPATCH(dispatch_restricted, P, w, colour, iter, slot, ident, s);
 }
 
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s) {

@@ -103,7 +103,7 @@ def _call(name, *args):
 
 
 TIMER_KINDS = ["features", "init", "eval_cost", "pm_init", "pm_restricted", "ransac", "assign", "symmetry", "fb",
-               "nnf_update", "finalize"]
+               "nnf_update", "finalize", "pm_list", "pm_restricted_ident"]
 
 
 def timing_enable(on: bool = True):
@@ -205,7 +205,8 @@ class Pair:
         """Warped-patch evaluations of the last pipeline run, per direction."""
         c = self._view(self.L.counters, 16 * 64, torch.int64).cpu().numpy().reshape(16, 64).sum(axis=1)
         return {"pm_init": c[0:2].tolist(), "eval_cost": c[2:4].tolist(), "pm_restricted": c[4:6].tolist(),
-                "pm_init_rows": c[6:8].tolist(), "pm_restricted_rows": c[8:10].tolist()}
+                "pm_init_rows": c[6:8].tolist(), "pm_restricted_rows": c[8:10].tolist(),
+                "pm_restricted_ident": c[10:12].tolist(), "pm_restricted_ident_rows": c[12:14].tolist()}
 
     def features(self, f) -> np.ndarray:
         """Features of frame f as (H, W, C) float32 on the host."""
