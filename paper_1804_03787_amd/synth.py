@@ -204,6 +204,20 @@ def ground_truth(layers, W, H, top1=None, return_cover=False, step=1):
 # Workloads
 # --------------------------------------------------------------------------
 
+def ground_truth_backward(layers, W, H):
+    """Ground-truth flow from frame 2 to frame 1: a frame-2 pixel q belongs to
+    the top layer whose pre-image H^-1 q lies in its support (the background
+    otherwise), and moves to that pre-image."""
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    top2, pre = _top_layer_frame2(layers, xs, ys)
+    flow = np.zeros((H, W, 2))
+    for i in range(len(layers)):
+        m = top2 == i
+        flow[m, 0] = pre[i][0][m] - xs[m]
+        flow[m, 1] = pre[i][1][m] - ys[m]
+    return flow.astype(np.float32)
+
+
 def tiny_pair(seed: int = 0) -> Pair:
     """128x96: background translated by (+5, +3); right half (x >= 64) zoomed by
     5 % and rotated by 3 degrees about (96, 48); a 20x20 occluder over

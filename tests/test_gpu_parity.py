@@ -53,6 +53,9 @@ CASES = {
     "tiny_c5": (lambda: synth.tiny_pair(0), TINY_PARAMS),
     "tiny_c3": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, C=3, grad_weight=0.0)),
     "ragged": (_ragged_pair, RAGGED),
+    # FP16 feature storage with FP32 accumulation, against the oracle on the
+    # same FP16-rounded features
+    "tiny_c5_fp16": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fp16=True)),
 }
 
 
