@@ -82,6 +82,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
+    ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not supported "
@@ -94,7 +95,7 @@ def main() -> int:
     from paper_1804_03787_amd import msgpm, synth
 
     msgpm.lib()  # fails loudly if the HIP library is missing
-    pair = synth.planar_pair(W, H, seed=0)
+    pair = synth.planar_pair(W, H, seed=args.seed)
     f1 = torch.from_numpy(pair.frame1).cuda()
     f2 = torch.from_numpy(pair.frame2).cuda()
     params = dict(PARAMS, fp16=args.fp16)
@@ -172,7 +173,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
                                "8 PM iterations, 256 RANSAC hypotheses",
-                   "width": W, "height": H, "seed": 0, "fp16_storage": bool(args.fp16)},
+                   "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16)},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
         "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},

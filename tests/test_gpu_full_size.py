@@ -1,6 +1,7 @@
 """GPU parity at the size and parameters of the benchmark workload (a
 1024x436 pair, 9x9 patches over 5 channels, windows 64/32/16, 256 RANSAC
-hypotheses): the same launch configuration as bench.py, phases fed the
+hypotheses), in its plain FP32 form (scene seed 0) and its FP16-storage form
+(scene seed 1): the same launch configuration as bench.py, phases fed the
 oracle's exact state and compared as in the small lock-step tests.
 
 The oracle needs about 25 s per PatchMatch half-sweep at this size, so these
@@ -27,11 +28,15 @@ pytestmark = pytest.mark.gpu
 
 W, H = 1024, 436
 FULL = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0, seed=0)
+# (scene seed, FP16 feature storage): the plain FP32 workload and its FP16-storage precision form
+FORMS = {"fp32_seed0": (0, False), "fp16_seed1": (1, True)}
+_pairs = {}
 
 
-@pytest.fixture(scope="module")
-def pair():
-    return synth.planar_pair(W, H, seed=0)
+def _pair(seed):
+    if seed not in _pairs:
+        _pairs[seed] = synth.planar_pair(W, H, seed=seed)
+    return _pairs[seed]
 
 
 def _lockstep(o, g, steps, p):
@@ -49,25 +54,42 @@ def _lockstep(o, g, steps, p):
     return report
 
 
-def _start(msgpm, pair):
-    o = oracle.Oracle(pair.frame1, pair.frame2, **FULL)
-    g = msgpm.Pair(W, H, **_gpu_params(FULL))
+def _start(msgpm, pair, p):
+    o = oracle.Oracle(pair.frame1, pair.frame2, **p)
+    g = msgpm.Pair(W, H, **_gpu_params(p))
     g.set_features(pair.frame1, pair.frame2)
     for f in range(2):
         assert np.array_equal(g.features(f).view(np.uint32), o.feat[f].view(np.uint32))
     return o, g
 
 
-def test_full_size_initial_pass_step(pair):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_full_size_initial_pass_step(form):
     msgpm = _need_gpu()
-    o, g = _start(msgpm, pair)
+    seed, fp16 = FORMS[form]
+    pair = _pair(seed)
+    p = dict(FULL, fp16=fp16)
+    o, g = _start(msgpm, pair, p)
     g.init_state()
     for d in range(2):
         o.nnf_init(d)
         assert np.array_equal(g.nnf(d).cpu().numpy(), o.nnf[d])
-    report = _lockstep(o, g, [("eval_cost", (0,)), ("pm_halfsweep", (0, 0, 0, 0))], FULL)
-    assert report["steps"] == 2 and report["pm_unexplained"] == 0
-    print("full-size initial pass", report)
+    report = _lockstep(o, g, [("eval_cost", (0,))], p)
+    if fp16:
+        # precision of the FP16 storage: the same costs from the oracle on the FP32 features
+        o32 = oracle.Oracle(pair.frame1, pair.frame2, **FULL)
+        for d in range(2):
+            o32.set_nnf(d, o.nnf[d])
+            o32.eval_cost(d, 0)
+            got = g.cost(d).cpu().numpy().astype(np.float64)
+            rel = np.abs(got - o32.cost[d]) / np.maximum(np.abs(o32.cost[d]), 1e-12)
+            q = np.quantile(rel, [0.5, 0.99, 1.0])
+            print(f"FP16 storage, cost relative error against FP32 features, dir {d}: "
+                  f"median {q[0]:.2e}, p99 {q[1]:.2e}, max {q[2]:.2e}")
+            assert q[0] < 1e-3
+    report = _lockstep(o, g, [("pm_halfsweep", (0, 0, 0, 0))], p)
+    assert report["pm_unexplained"] == 0
+    print("full-size initial pass", form, report)
 
 
 def _perturbed_nnf(flow, seed, frac=0.2, amp=16):
@@ -80,9 +102,13 @@ def _perturbed_nnf(flow, seed, frac=0.2, amp=16):
     return oracle.pack(dx, dy)
 
 
-def test_full_size_plane_phases(pair):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_full_size_plane_phases(form):
     msgpm = _need_gpu()
-    o, g = _start(msgpm, pair)
+    seed, fp16 = FORMS[form]
+    pair = _pair(seed)
+    p = dict(FULL, fp16=fp16)
+    o, g = _start(msgpm, pair, p)
     init = [_perturbed_nnf(pair.flow, 1), _perturbed_nnf(synth.ground_truth_backward(pair.layers, W, H), 2)]
     g.init_state(torch.from_numpy(init[0]), torch.from_numpy(init[1]))
     for d in range(2):
@@ -96,7 +122,7 @@ def test_full_size_plane_phases(pair):
         steps += [("fb_unassign", ()), ("nnf_update", (lv,))]
         if lv == 0:
             steps += [("eval_cost", (1,)), ("pm_halfsweep", (0, 0, 1, 1))]
-    report = _lockstep(o, g, steps, FULL)
+    report = _lockstep(o, g, steps, p)
     assert report["pm_unexplained"] == 0
     # the steps did real work: most pixels end up on a plane, some windows needed stage 2
     pl = parity.planes_to_gpu(o)
@@ -112,4 +138,28 @@ def test_full_size_plane_phases(pair):
         asg = o.win[d] >= 0
         tol = parity.cost_tol(o.cost[d], FULL["r"], FULL["C"])
         assert (np.abs(c - o.cost[d])[asg] <= tol[asg]).all()
-    print("full-size plane phases", report, "assigned", float((o.win[0] >= 0).mean()))
+    print("full-size plane phases", form, report, "assigned", float((o.win[0] >= 0).mean()))
+
+
+def test_full_size_fp16_storage_against_fp32_form():
+    """Whole pipeline at full size, scene seed 1: the FP16-storage form against
+    the plain FP32 GPU form (the oracle needs tens of minutes for a whole
+    pipeline at this size; its parity is covered step by step above)."""
+    msgpm = _need_gpu()
+    pair = _pair(1)
+    out = {}
+    for fp16 in (False, True):
+        g = msgpm.Pair(W, H, **_gpu_params(dict(FULL, fp16=fp16)))
+        flows, occs = g.solve(pair.frame1, pair.frame2)
+        torch.cuda.synchronize()
+        out[fp16] = (flows[0].cpu().numpy(), occs[0].cpu().numpy())
+    (f32, o32), (f16, o16) = out[False], out[True]
+    vis = pair.occ == 0
+    both = (o16 == 0) & (o32 == 0)
+    delta = np.linalg.norm(f16 - f32, axis=-1)[both].mean()
+    epe16 = np.linalg.norm(f16 - pair.flow, axis=-1)[vis & (o16 == 0)].mean()
+    epe32 = np.linalg.norm(f32 - pair.flow, axis=-1)[vis & (o32 == 0)].mean()
+    agree = (o16 == o32).mean()
+    print(f"full size, FP16 storage vs FP32 form: mean flow delta {delta:.4f} px, EPE to ground truth "
+          f"{epe16:.4f} vs {epe32:.4f} px, occlusion agreement {agree:.4f}")
+    assert abs(epe16 - epe32) < 0.05 and agree > 0.95

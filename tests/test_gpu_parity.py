@@ -188,7 +188,7 @@ def test_lockstep_pipeline(case):
     print(case, report)
 
 
-@pytest.mark.parametrize("case", ["tiny_c5"])
+@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16"])
 def test_solve_end_to_end(case):
     """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
     so the comparison is statistical: offsets, masks and flows of the GPU run
@@ -237,3 +237,32 @@ def test_invalid_arguments_raise():
         g.ransac(3, 1)
     with pytest.raises(msgpm.MsgpmError):
         g.pm_halfsweep(2, 0, 0, 0)
+
+
+def test_fp16_storage_precision_report():
+    """What FP16 feature storage costs in the flow: the GPU's FP16-storage
+    solve against the oracle on the FP32 features and against the GPU's FP32
+    form (the FP16 form against the oracle on the same FP16 features is held to
+    the parity bar above).  Reported; bounded loosely."""
+    msgpm = _need_gpu()
+    pair = synth.tiny_pair(0)
+    p16 = dict(TINY_PARAMS, fp16=True)
+    fo32, oo32 = oracle.Oracle(pair.frame1, pair.frame2, **TINY_PARAMS).solve()
+    g16 = msgpm.Pair(128, 96, **_gpu_params(p16))
+    fg16, og16 = g16.solve(pair.frame1, pair.frame2)
+    g32 = msgpm.Pair(128, 96, **_gpu_params(TINY_PARAMS))
+    fg32, og32 = g32.solve(pair.frame1, pair.frame2)
+    torch.cuda.synchronize()
+    gt = pair.flow
+    vis = pair.occ == 0
+    for name, (fr, orr) in {"oracle FP32 features": (fo32[0], oo32[0]),
+                            "GPU FP32 form": (fg32[0].cpu().numpy(), og32[0].cpu().numpy())}.items():
+        f16, o16 = fg16[0].cpu().numpy(), og16[0].cpu().numpy()
+        both = (o16 == 0) & (orr == 0)
+        delta = np.linalg.norm(f16 - fr, axis=-1)[both].mean()
+        epe16 = np.linalg.norm(f16 - gt, axis=-1)[vis & (o16 == 0)].mean()
+        eperef = np.linalg.norm(fr - gt, axis=-1)[vis & (orr == 0)].mean()
+        agree = (o16 == orr).mean()
+        print(f"FP16 storage vs {name}: mean flow delta {delta:.4f} px, EPE to ground truth "
+              f"{epe16:.4f} vs {eperef:.4f} px, occlusion agreement {agree:.4f}")
+        assert delta < 0.25 and abs(epe16 - eperef) < 0.25 and agree > 0.95
