@@ -202,6 +202,32 @@ msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, f
                             uint8_t* d_occ1, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched solves: the pipeline of msgpm_solve for n frame pairs at once, one
+ * launch per phase covering every pair (pairs of different sizes share the
+ * launches; small pairs then fill the GPU together).  Each pair has its own
+ * parameters, workspace (layout from msgpm_layout_query on its parameters),
+ * frames, optional initial NNF and outputs, exactly as for msgpm_solve, and its
+ * results are identical to a msgpm_solve of that pair alone.  All pairs must
+ * share patch_radius, channels, the FP16 flag, pm_iters and n_levels.
+ *   params:          n parameter sets (host array).
+ *   d_rgb1 .. d_occ1: host arrays of n device pointers each; d_init_nnf0/1 may
+ *                    be NULL (random initial NNF for every pair) or hold NULL
+ *                    entries.
+ *   d_scratch:       device buffer of the size msgpm_batch_query returns,
+ *                    256-byte aligned, for the launch tables; it must stay
+ *                    untouched until the work enqueued here has run.
+ * The launch tables are copied to d_scratch through a pinned host buffer that
+ * the library keeps (and reuses once the previous upload has completed).
+ * Work is enqueued on `stream`; errors as for msgpm_solve.
+ * ------------------------------------------------------------------------- */
+msgpm_status msgpm_batch_query(int n, const msgpm_params* params, uint64_t* scratch_bytes);
+msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* const* d_rgb1,
+                               const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
+                               const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
+                               float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                               void* d_scratch, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing.  While enabled, the library records a pair of HIP events on
  * the launch stream around every kernel it launches (from any entry point) and
  * attributes the elapsed time to one of the kinds below.  msgpm_timing_read

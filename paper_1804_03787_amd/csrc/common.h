@@ -46,6 +46,51 @@ struct Ws {
   unsigned* act_count;    // list lengths [direction][with region plane, without]
 };
 
+// Batched launches: one launch covers the same phase of several frame pairs.
+// A pair is described by a PairDesc (its parameters, workspace and buffers);
+// its share of a launch is an Item: workgroups [start, start + nb) of the grid
+// (start a multiple of kXcds, so that XCD-aware remaps within a pair stay
+// valid; the workgroups up to the next item's start exit) and the phase's
+// arguments.
+struct PairDesc {
+  DevParams P;
+  Ws w;
+  const float* rgb[2];
+  const int32_t* init[2];
+  float* flow[2];
+  uint8_t* occ[2];
+};
+struct Item {
+  int pair, start, nb;
+  int a[5];
+};
+
+// Workgroup coordinates within its pair's part of a launch.
+struct Blk {
+  int x, nx, y;
+};
+__device__ inline Blk blk_here() { return Blk{(int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y}; }
+
+// The item owning this workgroup (items sorted by start; n >= 1).
+__device__ inline int find_item(const Item* __restrict__ it, int n) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (it[mid].start <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Resolves a batched launch's workgroup: false for a padding workgroup.
+__device__ inline bool batch_blk(const Item* __restrict__ it, int n, int& i, Blk& b) {
+  i = find_item(it, n);
+  const int lb = (int)blockIdx.x - it[i].start;
+  b = Blk{lb, it[i].nb, (int)blockIdx.y};
+  return lb < it[i].nb;
+}
+
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 __host__ __device__ inline int32_t pack_off(int dx, int dy) {
@@ -136,5 +181,40 @@ hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s);
 hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
                            uint8_t* occ1, hipStream_t s);
+
+// ---- batched launches -------------------------------------------------------
+enum BatchKind {
+  BK_FEATURES,      // grid.y = frame
+  BK_INIT_PIXELS,
+  BK_INIT_PLANES,   // grid.y = 1
+  BK_EVAL_COST_IDENT,  // a = {0}: identity-patch cost refresh
+  BK_EVAL_COST_PLANE,  // a = {mode 1 or 2}: region-plane cost refresh
+  BK_ZERO_ACTIVE,   // one workgroup per item, grid.y = 1
+  BK_ACTIVE_LIST,   // a = {colour}
+  BK_PM_INIT,       // a = {colour, iter, slot, 0}
+  BK_PM_RESTRICTED, // a = {colour, iter, slot, 1}: pixels with a region plane
+  BK_PM_RESTRICTED_IDENT,  // the same, pixels without one
+  BK_RANSAC,        // a = {level, stage}
+  BK_ASSIGN,        // a = {level, stage, tentative}
+  BK_SYMMETRY,      // a = {level, stage}
+  BK_FB,
+  BK_COMMIT,
+  BK_NNF_UPDATE,    // a = {level}
+  BK_FINALIZE,
+  BK_KINDS
+};
+// Workgroups (x) one pair needs for kernel `kind` with arguments a; grid.y.
+int batch_blocks(int kind, const DevParams& P, const int* a);
+int batch_grid_y(int kind);
+// One batched launch over `total` workgroups; `lds`: dynamic LDS (RANSAC).
+// P0 selects the kernel instantiation (r, C, storage), equal for every pair.
+hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
+                          size_t lds, hipStream_t s);
+hipError_t launch_batched_init(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s);
+hipError_t launch_batched_pm(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
+                             hipStream_t s);
+hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, int n, int total, size_t lds,
+                                 hipStream_t s);
+size_t ransac_smem_bytes(const DevParams& P, int level);
 
 }  // namespace msgpm

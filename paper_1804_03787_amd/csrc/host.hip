@@ -11,10 +11,6 @@
 
 #include "common.h"
 
-namespace msgpm {
-size_t ransac_smem_bytes(const DevParams& P, int level);
-}
-
 using namespace msgpm;
 
 namespace {
@@ -380,6 +376,200 @@ msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float
   RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 2, c.s); }), "eval_cost");
   RUN(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 #undef RUN
+  return MSGPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---- batched solves ----------------------------------------------------------
+struct BatchStep {
+  int kind, timer;
+  int a[5];
+};
+
+// The launch sequence of msgpm_solve, as batched kernel kinds.
+std::vector<BatchStep> batch_schedule(const DevParams& P) {
+  std::vector<BatchStep> v;
+  auto add = [&](int kind, int timer, int a0 = 0, int a1 = 0, int a2 = 0, int a3 = 0) {
+    v.push_back(BatchStep{kind, timer, {a0, a1, a2, a3, 0}});
+  };
+  add(BK_FEATURES, MSGPM_T_FEATURES);
+  add(BK_INIT_PIXELS, MSGPM_T_INIT);
+  add(BK_INIT_PLANES, MSGPM_T_INIT);
+  add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 0);
+  for (int it = 0; it < P.iters; ++it)
+    for (int colour = 0; colour < 2; ++colour) add(BK_PM_INIT, MSGPM_T_PM_INIT, colour, it, 0, 0);
+  for (int l = 0; l < P.n_levels; ++l) {
+    for (int stage = 1; stage <= 2; ++stage) {
+      add(BK_RANSAC, MSGPM_T_RANSAC, l, stage);
+      add(BK_ASSIGN, MSGPM_T_ASSIGN, l, stage, 1);
+      add(BK_SYMMETRY, MSGPM_T_SYMMETRY, l, stage);
+      add(BK_ASSIGN, MSGPM_T_ASSIGN, l, stage, 0);
+    }
+    add(BK_FB, MSGPM_T_FB);
+    add(BK_COMMIT, MSGPM_T_FB);
+    add(BK_NNF_UPDATE, MSGPM_T_NNF_UPDATE, l);
+    add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
+    for (int it = 0; it < P.iters; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        add(BK_ZERO_ACTIVE, MSGPM_T_PM_LIST);
+        add(BK_ACTIVE_LIST, MSGPM_T_PM_LIST, colour);
+        add(BK_PM_RESTRICTED, MSGPM_T_PM_RESTRICTED, colour, it, l + 1, 1);
+        add(BK_PM_RESTRICTED_IDENT, MSGPM_T_PM_RESTRICTED_IDENT, colour, it, l + 1, 1);
+      }
+  }
+  add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 2);
+  add(BK_FINALIZE, MSGPM_T_FINALIZE);
+  return v;
+}
+
+// Validates a batch and derives each pair's kernel parameters.
+msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevParams>& P,
+                           std::vector<msgpm_layout>& L) {
+  if (n < 1 || n > 4096) return fail(MSGPM_E_INVALID, "batch size %d outside 1..4096", n);
+  if (!params) return fail(MSGPM_E_INVALID, "params is NULL");
+  P.resize(n);
+  L.resize(n);
+  for (int i = 0; i < n; ++i) {
+    msgpm_status st = prepare(&params[i], &P[i], &L[i]);
+    if (st != MSGPM_OK) return fail(st, "pair %d: %s", i, g_err.c_str());
+    const DevParams& a = P[0];
+    const DevParams& b = P[i];
+    if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels)
+      return fail(MSGPM_E_INVALID,
+                  "pair %d: a batch needs one patch radius, channel count, storage, iteration count and level count",
+                  i);
+  }
+  return MSGPM_OK;
+}
+
+// Item table of one batch: per step, one item per pair.
+struct BatchPlan {
+  std::vector<BatchStep> steps;
+  std::vector<int> total;    // workgroups of each step's launch
+  std::vector<size_t> lds;   // dynamic LDS of each step's launch
+  uint64_t items = 0;        // items of all steps (n per step)
+  uint64_t bytes = 0;        // scratch: descriptors, then items
+};
+
+BatchPlan batch_plan(int n, const std::vector<DevParams>& P, std::vector<Item>* items) {
+  BatchPlan b;
+  b.steps = batch_schedule(P[0]);
+  for (const BatchStep& st : b.steps) {
+    int start = 0;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      Item it;
+      memset(&it, 0, sizeof it);
+      it.pair = i;
+      it.nb = batch_blocks(st.kind, P[i], st.a);
+      it.start = st.kind == BK_ZERO_ACTIVE ? i : start;
+      for (int k = 0; k < 5; ++k) it.a[k] = st.a[k];
+      start += (it.nb + kXcds - 1) / kXcds * kXcds;
+      if (st.kind == BK_RANSAC) {
+        const size_t m = ransac_smem_bytes(P[i], st.a[0]);
+        lds = m > lds ? m : lds;
+      }
+      if (items) items->push_back(it);
+    }
+    b.total.push_back(st.kind == BK_ZERO_ACTIVE ? n : start);
+    b.lds.push_back(lds);
+  }
+  b.items = (uint64_t)b.steps.size() * n;
+  b.bytes = align256((uint64_t)n * sizeof(PairDesc)) + b.items * sizeof(Item);
+  return b;
+}
+
+// Pinned staging buffer for the descriptor upload; reused once the previous
+// upload (recorded by `done`) has completed.
+struct Staging {
+  std::mutex mu;
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+};
+Staging g_staging;
+
+}  // namespace
+
+extern "C" {
+
+msgpm_status msgpm_batch_query(int n, const msgpm_params* params, uint64_t* scratch_bytes) {
+  if (!scratch_bytes) return fail(MSGPM_E_INVALID, "scratch_bytes is NULL");
+  std::vector<DevParams> P;
+  std::vector<msgpm_layout> L;
+  msgpm_status st = batch_prepare(n, params, P, L);
+  if (st != MSGPM_OK) return st;
+  *scratch_bytes = batch_plan(n, P, nullptr).bytes;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* const* d_rgb1,
+                               const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
+                               const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
+                               float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                               void* d_scratch, void* stream) {
+  std::vector<DevParams> P;
+  std::vector<msgpm_layout> L;
+  msgpm_status st = batch_prepare(n, params, P, L);
+  if (st != MSGPM_OK) return st;
+  if (!d_rgb1 || !d_rgb2 || !d_ws || !d_flow0 || !d_flow1 || !d_occ0 || !d_occ1)
+    return fail(MSGPM_E_INVALID, "pointer array is NULL");
+  if (!d_scratch || (reinterpret_cast<uintptr_t>(d_scratch) & 255))
+    return fail(MSGPM_E_INVALID, "scratch is NULL or not 256-byte aligned");
+  std::vector<Item> items;
+  const BatchPlan plan = batch_plan(n, P, &items);
+  std::vector<PairDesc> desc(n);
+  for (int i = 0; i < n; ++i) {
+    if (!d_ws[i] || (reinterpret_cast<uintptr_t>(d_ws[i]) & 255))
+      return fail(MSGPM_E_INVALID, "pair %d: workspace is NULL or not 256-byte aligned", i);
+    if (!d_rgb1[i] || !d_rgb2[i] || !d_flow0[i] || !d_flow1[i] || !d_occ0[i] || !d_occ1[i])
+      return fail(MSGPM_E_INVALID, "pair %d: frame or output pointer is NULL", i);
+    memset(&desc[i], 0, sizeof(PairDesc));
+    desc[i].P = P[i];
+    desc[i].w = make_ws(P[i], L[i], d_ws[i]);
+    desc[i].rgb[0] = d_rgb1[i];
+    desc[i].rgb[1] = d_rgb2[i];
+    desc[i].init[0] = d_init_nnf0 ? d_init_nnf0[i] : nullptr;
+    desc[i].init[1] = d_init_nnf1 ? d_init_nnf1[i] : nullptr;
+    desc[i].flow[0] = d_flow0[i];
+    desc[i].flow[1] = d_flow1[i];
+    desc[i].occ[0] = d_occ0[i];
+    desc[i].occ[1] = d_occ1[i];
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t desc_bytes = align256((uint64_t)n * sizeof(PairDesc));
+  char* dev = static_cast<char*>(d_scratch);
+  {
+    std::lock_guard<std::mutex> lk(g_staging.mu);
+    if (g_staging.done && (st = check(hipEventSynchronize(g_staging.done), "staging")) != MSGPM_OK) return st;
+    if (g_staging.cap < plan.bytes) {
+      if (g_staging.host) (void)hipHostFree(g_staging.host);
+      g_staging.host = nullptr;
+      g_staging.cap = 0;
+      if ((st = check(hipHostMalloc(&g_staging.host, plan.bytes, hipHostMallocDefault), "staging")) != MSGPM_OK)
+        return st;
+      g_staging.cap = plan.bytes;
+    }
+    if (!g_staging.done && (st = check(hipEventCreateWithFlags(&g_staging.done, hipEventDisableTiming), "staging")) !=
+                               MSGPM_OK)
+      return st;
+    char* h = static_cast<char*>(g_staging.host);
+    memcpy(h, desc.data(), (size_t)n * sizeof(PairDesc));
+    memcpy(h + desc_bytes, items.data(), items.size() * sizeof(Item));
+    if ((st = check(hipMemcpyAsync(dev, h, plan.bytes, hipMemcpyHostToDevice, s), "upload")) != MSGPM_OK) return st;
+    if ((st = check(hipEventRecord(g_staging.done, s), "staging")) != MSGPM_OK) return st;
+  }
+  const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
+  const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
+  for (size_t k = 0; k < plan.steps.size(); ++k) {
+    const BatchStep& bs = plan.steps[k];
+    st = check(timed(bs.timer, s, [&] { return launch_batched(bs.kind, P[0], pd, it + k * n, n, plan.total[k], plan.lds[k], s); }),
+               "batched launch");
+    if (st != MSGPM_OK) return st;
+  }
   return MSGPM_OK;
 }
 

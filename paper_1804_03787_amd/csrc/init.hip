@@ -22,9 +22,9 @@ __device__ inline float luma(const float* rgb, int p) {
   return (t + u) + v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ rgb, int W, int H, int C, int fp16,
-                                                    void* __restrict__ feat) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void features_body(const float* __restrict__ rgb, int W, int H, int C, int fp16,
+                                              void* __restrict__ feat, Blk bk) {
+  const int p = bk.x * kBlock + threadIdx.x;
   const int n = W * H;
   if (p > n) return;
   float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -50,6 +50,21 @@ __global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ r
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ rgb, int W, int H, int C, int fp16,
+                                                    void* __restrict__ feat) {
+  features_body(rgb, W, H, C, fp16, feat, blk_here());
+}
+
+// batched: grid.y = frame
+__global__ __launch_bounds__(kBlock) void kb_features(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                     int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  features_body(D.rgb[bk.y], D.P.W, D.P.H, D.P.C, D.P.fp16, const_cast<void*>(D.w.feat[bk.y]), bk);
+}
+
 hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s) {
   const int n = P.W * P.H + 1;  // pixels plus the zero pad pixel
   hipLaunchKernelGGL(k_features, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rgb, P.W, P.H, P.C, P.fp16,
@@ -59,10 +74,10 @@ hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hip
 
 // Initial NNF: caller's offsets with targets clamped into the frame, or a
 // uniform random target per pixel from the Philox stream (phase 1, draw 0).
-__global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const int32_t* __restrict__ init0,
-                                                       const int32_t* __restrict__ init1) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
-  const int dir = blockIdx.y;
+__device__ __forceinline__ void init_pixels_body(const DevParams& P, const Ws& w, const int32_t* __restrict__ init0,
+                                                 const int32_t* __restrict__ init1, Blk bk) {
+  const int p = bk.x * kBlock + threadIdx.x;
+  const int dir = bk.y;
   const int W = P.W, H = P.H;
   if (p >= W * H) return;
   const int x = p % W, y = p / W;
@@ -87,10 +102,23 @@ __global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const
   w.cost[dir][p] = 0.f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  for (int c = blockIdx.x * kBlock + threadIdx.x; c < kCounterKinds * kCounterStripes; c += gridDim.x * kBlock)
-    w.counters[c] = 0;
+__global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const int32_t* __restrict__ init0,
+                                                       const int32_t* __restrict__ init1) {
+  init_pixels_body(P, w, init0, init1, blk_here());
+}
+
+__global__ __launch_bounds__(kBlock) void kb_init_pixels(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                        int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  init_pixels_body(D.P, D.w, D.init[0], D.init[1], bk);
+}
+
+__device__ __forceinline__ void init_planes_body(const DevParams& P, const Ws& w, Blk bk) {
+  const int k = bk.x * kBlock + threadIdx.x;
+  for (int c = k; c < kCounterKinds * kCounterStripes; c += bk.nx * kBlock) w.counters[c] = 0;
   if (k >= 2 * P.planes_per_dir) return;
   const int dir = k / P.planes_per_dir;
   int r = k - dir * P.planes_per_dir;
@@ -118,6 +146,17 @@ __global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) {
   w.planes[k] = pl;
 }
 
+__global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) { init_planes_body(P, w, blk_here()); }
+
+__global__ __launch_bounds__(kBlock) void kb_init_planes(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                        int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  init_planes_body(D.P, D.w, bk);
+}
+
 hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
                              hipStream_t s) {
   const int n = P.W * P.H;
@@ -127,6 +166,23 @@ hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* ini
   const int np = 2 * P.planes_per_dir;
   const int nblk = np > kBlock ? np : kBlock;
   hipLaunchKernelGGL(k_init_planes, dim3((nblk + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_init(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s) {
+  switch (kind) {
+    case BK_FEATURES:
+      hipLaunchKernelGGL(kb_features, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      break;
+    case BK_INIT_PIXELS:
+      hipLaunchKernelGGL(kb_init_pixels, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      break;
+    case BK_INIT_PLANES:
+      hipLaunchKernelGGL(kb_init_planes, dim3(total, 1), dim3(kBlock), 0, s, pd, it, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -341,13 +341,13 @@ __device__ inline float group_cost(const LaneCol<R, C, IDENT>& L, Feat F2, int W
 // Cost refresh: cost[p] = C(p, p + v_p, H_p) for the selected pixels.
 // ---------------------------------------------------------------------------
 template <int R, int C, bool FP16, bool IDENT>
-__global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mode) {
+__device__ __forceinline__ void eval_cost_body(const DevParams& P, const Ws& w, Blk bk, int mode) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int g = lane / G, j = lane - g * G, base = g * G;
-  const int dir = blockIdx.y;
+  const int dir = bk.y;
   const int W = P.W, H = P.H;
-  const long long i = ((long long)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + wave) * NG + g;
+  const long long i = ((long long)xcd_remap(bk.x, bk.nx) * (kBlock / kWave) + wave) * NG + g;
   bool act = g < NG && i < (long long)W * H;
   const int p = act ? (int)i : 0, x = p % W, y = p / W;
   int label = -1;
@@ -385,6 +385,20 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
     }
   }
   count_evals<true>(w.counters, 2 + dir, evals);
+}
+
+template <int R, int C, bool FP16, bool IDENT>
+__global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mode) {
+  eval_cost_body<R, C, FP16, IDENT>(P, w, blk_here(), mode);
+}
+
+template <int R, int C, bool FP16, bool IDENT>
+__global__ __launch_bounds__(kBlock) void kb_eval_cost(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                      int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  eval_cost_body<R, C, FP16, IDENT>(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
 }
 
 // Candidate loops of one pixel: the four neighbours' offsets (left, right, up,
@@ -589,13 +603,18 @@ __global__ void k_zero_active(Ws w) {
   if (threadIdx.x < 4) w.act_count[threadIdx.x] = 0u;
 }
 
+// batched: one workgroup per item
+__global__ void kb_zero_active(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  if (threadIdx.x < 4 && (int)blockIdx.x < n) pd[it[blockIdx.x].pair].w.act_count[threadIdx.x] = 0u;
+}
+
 constexpr int kListSpan = 4;  // pixels of the colour per thread of k_active_list
 
-__global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int colour) {
+__device__ __forceinline__ void active_list_body(const DevParams& P, const Ws& w, Blk bk, int colour) {
   constexpr int NS = kListSpan * (kBlock / kWave);
   __shared__ int s_cnt[2][NS];
   __shared__ unsigned s_base[2];
-  const int dir = blockIdx.y;
+  const int dir = bk.y;
   const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
   const unsigned cap = (unsigned)Wh * (unsigned)H;
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
@@ -604,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int c
   unsigned long long mA[kListSpan], mB[kListSpan];
 #pragma unroll
   for (int k = 0; k < kListSpan; ++k) {
-    const long long i = ((long long)blockIdx.x * kListSpan + k) * kBlock + t;
+    const long long i = ((long long)bk.x * kListSpan + k) * kBlock + t;
     bool act = i < (long long)cap;
     pix[k] = 0;
     bool plane = false;
@@ -646,6 +665,18 @@ __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int c
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int colour) {
+  active_list_body(P, w, blk_here(), colour);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_active_list(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                        int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  active_list_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+}
+
 // ---------------------------------------------------------------------------
 // One red-black half-sweep over the pixels of one colour, both directions
 // (restricted: over the listed pixels).
@@ -653,12 +684,12 @@ __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int c
 // The distorted-patch form is held to 168 VGPRs (3 waves per SIMD): on MI355X
 // the extra wave hides more gather latency than the few registers it costs.
 template <int R, int C, bool FP16, bool IDENT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void k_pm_halfsweep(DevParams P, Ws w, int colour, int iter, int slot,
-                                                        int restricted) {
+__device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& w, Blk bk, int colour, int iter,
+                                                  int slot, int restricted) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int g = lane / G, j = lane - g * G, base = g * G;
-  const int dir = blockIdx.y;
+  const int dir = bk.y;
   const int W = P.W, H = P.H, Wh = (W + 1) >> 1;
   bool act;
   int x, y;
@@ -668,15 +699,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
     const unsigned cnt = w.act_count[2 * dir + (IDENT ? 1 : 0)];
     constexpr unsigned per = NG * (kBlock / kWave);
     const int nb = (int)((cnt + per - 1) / per);
-    if ((int)blockIdx.x >= nb) return;
-    const long long i = ((long long)xcd_remap(blockIdx.x, nb) * (kBlock / kWave) + wave) * NG + g;
+    if (bk.x >= nb) return;
+    const long long i = ((long long)xcd_remap(bk.x, nb) * (kBlock / kWave) + wave) * NG + g;
     act = g < NG && i < (long long)cnt;
     const unsigned cap = (unsigned)Wh * (unsigned)H;
     const int q = act ? w.act[dir][IDENT ? cap - 1u - (unsigned)i : (unsigned)i] : 0;
     y = q / W;
     x = q - y * W;
   } else {
-    const long long i = ((long long)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + wave) * NG + g;
+    const long long i = ((long long)xcd_remap(bk.x, bk.nx) * (kBlock / kWave) + wave) * NG + g;
     act = g < NG && i < (long long)Wh * H;
     y = act ? (int)(i / Wh) : 0;
     x = act ? 2 * (int)(i - (long long)y * Wh) + ((y + colour) & 1) : 0;
@@ -744,6 +775,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
   }
   count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 10 : 4) : 0) + dir, evals);
   count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 12 : 8) : 6) + dir, rows);
+}
+
+template <int R, int C, bool FP16, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void k_pm_halfsweep(
+    DevParams P, Ws w, int colour, int iter, int slot, int restricted) {
+  pm_halfsweep_body<R, C, FP16, IDENT>(P, w, blk_here(), colour, iter, slot, restricted);
+}
+
+template <int R, int C, bool FP16, bool IDENT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void kb_pm_halfsweep(
+    const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  pm_halfsweep_body<R, C, FP16, IDENT>(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1], I.a[2], I.a[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -833,6 +880,63 @@ hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int
 
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s) {
   MSGPM_DISPATCH(dispatch_ec, P, w, mode, s);
+}
+
+template <int R, int C, bool FP16>
+static hipError_t dispatch_batched(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s) {
+  const dim3 grid(total, 2), block(kBlock);
+  switch (kind) {
+    case BK_PM_INIT:
+    case BK_PM_RESTRICTED_IDENT:
+      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, true>), grid, block, 0, s, pd, it, n);
+      break;
+    case BK_PM_RESTRICTED:
+      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, false>), grid, block, 0, s, pd, it, n);
+      break;
+    case BK_EVAL_COST_IDENT:
+      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, true>), grid, block, 0, s, pd, it, n);
+      break;
+    case BK_EVAL_COST_PLANE:
+      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, false>), grid, block, 0, s, pd, it, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_pm(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
+                             hipStream_t s) {
+  if (kind == BK_ZERO_ACTIVE) {
+    hipLaunchKernelGGL(kb_zero_active, dim3(n), dim3(kWave), 0, s, pd, it, n);
+    return hipGetLastError();
+  }
+  if (kind == BK_ACTIVE_LIST) {
+    hipLaunchKernelGGL(kb_active_list, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+    return hipGetLastError();
+  }
+  const DevParams& P = P0;
+  MSGPM_DISPATCH(dispatch_batched, kind, pd, it, n, total, s);
+}
+
+// Workgroups of the PatchMatch-side kernels for one pair (the single-pair
+// launchers' grids).
+int pm_batch_blocks(int kind, const DevParams& P) {
+  const int G = 2 * P.r + 1, NG = kWave / G, per = NG * (kBlock / kWave);
+  const long long half = (long long)((P.W + 1) >> 1) * P.H;
+  switch (kind) {
+    case BK_EVAL_COST_IDENT:
+    case BK_EVAL_COST_PLANE:
+      return (int)(((long long)P.W * P.H + per - 1) / per);
+    case BK_ZERO_ACTIVE:
+      return 1;
+    case BK_ACTIVE_LIST: {
+      const long long span = (long long)kListSpan * kBlock;
+      return (int)((half + span - 1) / span);
+    }
+    default:
+      return (int)((half + per - 1) / per);
+  }
 }
 
 }  // namespace msgpm

@@ -491,7 +491,7 @@ __device__ inline void score_batch(const double* aux, const unsigned long long* 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
+__device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk bk, int level, int stage) {
   extern __shared__ double smem_d[];
   __shared__ int s_wave[kBlock / kWave];
   __shared__ int s_n, s_ni, s_ok, s_cnt_r;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
   __shared__ double s_ne[kNeSums];
 
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-  const int b = blockIdx.x, dir = blockIdx.y;
+  const int b = bk.x, dir = bk.y;
   const int W = P.W, Hh = P.H;
   const int B = P.block[level], nbx = P.nbx[level];
   const int bw = B < W ? B : W, bh = B < Hh ? B : Hh;
@@ -812,6 +812,18 @@ __global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level,
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
+  ransac_body(P, w, blk_here(), level, stage);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_ransac(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  ransac_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+}
+
 // ---------------------------------------------------------------------------
 // Assignment: per pixel, the minimum of the key (L, level, stage, window) over
 // the incumbent and the inlier planes of (level, stage) whose window covers p.
@@ -823,8 +835,8 @@ __device__ inline bool key_less(double L1, const msgpm_plane& a, double L2, cons
   return a.block < b.block;
 }
 
-__global__ __launch_bounds__(kBlock) void k_assign(DevParams P, Ws w, int level, int stage, int tentative) {
-  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+__device__ __forceinline__ void assign_body(const DevParams& P, const Ws& w, Blk bk, int level, int stage, int tentative) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   const int W = P.W, Hh = P.H;
   if (p >= W * Hh) return;
   const int x = p % W, y = p / W;
@@ -854,12 +866,24 @@ __global__ __launch_bounds__(kBlock) void k_assign(DevParams P, Ws w, int level,
   ol[p] = bwin >= 0 ? bl : __builtin_huge_val();
 }
 
+__global__ __launch_bounds__(kBlock) void k_assign(DevParams P, Ws w, int level, int stage, int tentative) {
+  assign_body(P, w, blk_here(), level, stage, tentative);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_assign(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  assign_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1], I.a[2]);
+}
+
 // ---------------------------------------------------------------------------
 // Plane symmetry: one workgroup per (window, direction).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_symmetry(DevParams P, Ws w, int level, int stage) {
+__device__ __forceinline__ void symmetry_body(const DevParams& P, const Ws& w, Blk bk, int level, int stage) {
   __shared__ int s_rk, s_pass;
-  const int t = threadIdx.x, b = blockIdx.x, dir = blockIdx.y;
+  const int t = threadIdx.x, b = bk.x, dir = bk.y;
   msgpm_plane* pl = &w.planes[plane_index(P, dir, level, stage, b)];
   if (t == 0) {
     s_rk = 0;
@@ -901,11 +925,23 @@ __global__ __launch_bounds__(kBlock) void k_symmetry(DevParams P, Ws w, int leve
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_symmetry(DevParams P, Ws w, int level, int stage) {
+  symmetry_body(P, w, blk_here(), level, stage);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_symmetry(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  symmetry_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+}
+
 // ---------------------------------------------------------------------------
 // End-of-level forward-backward check (Jacobi over both directions).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_fb(DevParams P, Ws w) {
-  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+__device__ __forceinline__ void fb_body(const DevParams& P, const Ws& w, Blk bk) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   if (p >= P.W * P.H) return;
   const int j = w.win[dir][p];
   int o = j;
@@ -918,18 +954,42 @@ __global__ __launch_bounds__(kBlock) void k_fb(DevParams P, Ws w) {
   w.tloss[dir][p] = l;
 }
 
-__global__ __launch_bounds__(kBlock) void k_commit(DevParams P, Ws w) {
-  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+__global__ __launch_bounds__(kBlock) void k_fb(DevParams P, Ws w) {
+  fb_body(P, w, blk_here());
+}
+
+__global__ __launch_bounds__(kBlock) void kb_fb(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  fb_body(pd[I.pair].P, pd[I.pair].w, bk);
+}
+
+__device__ __forceinline__ void commit_body(const DevParams& P, const Ws& w, Blk bk) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   if (p >= P.W * P.H) return;
   w.win[dir][p] = w.twin[dir][p];
   w.loss[dir][p] = w.tloss[dir][p];
 }
 
+__global__ __launch_bounds__(kBlock) void k_commit(DevParams P, Ws w) {
+  commit_body(P, w, blk_here());
+}
+
+__global__ __launch_bounds__(kBlock) void kb_commit(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  commit_body(pd[I.pair].P, pd[I.pair].w, bk);
+}
+
 // ---------------------------------------------------------------------------
 // NNF update from assigned planes and region plane choice.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_nnf_update(DevParams P, Ws w, int level) {
-  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+__device__ __forceinline__ void nnf_update_body(const DevParams& P, const Ws& w, Blk bk, int level) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   const int W = P.W, Hh = P.H;
   if (p >= W * Hh) return;
   const int x = p % W, y = p / W;
@@ -961,9 +1021,21 @@ __global__ __launch_bounds__(kBlock) void k_nnf_update(DevParams P, Ws w, int le
   if (best >= 0) w.hlabel[dir][p] = best;
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(DevParams P, Ws w, float* flow0, float* flow1, uint8_t* occ0,
-                                                    uint8_t* occ1) {
-  const int p = blockIdx.x * kBlock + threadIdx.x, dir = blockIdx.y;
+__global__ __launch_bounds__(kBlock) void k_nnf_update(DevParams P, Ws w, int level) {
+  nnf_update_body(P, w, blk_here(), level);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_nnf_update(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const Item& I = it[i];
+  nnf_update_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0]);
+}
+
+__device__ __forceinline__ void finalize_body(const DevParams& P, const Ws& w, Blk bk, float* flow0, float* flow1,
+                                              uint8_t* occ0, uint8_t* occ1) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   const int W = P.W;
   if (p >= W * P.H) return;
   const int x = p % W, y = p / W;
@@ -985,6 +1057,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(DevParams P, Ws w, float* f
     }
     if (occ) occ[p] = 1;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(DevParams P, Ws w, float* flow0, float* flow1, uint8_t* occ0,
+                                                    uint8_t* occ1) {
+  finalize_body(P, w, blk_here(), flow0, flow1, occ0, occ1);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_finalize(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  finalize_body(D.P, D.w, bk, D.flow[0], D.flow[1], D.occ[0], D.occ[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,6 +1123,91 @@ hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float*
                            uint8_t* occ1, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, pixel_grid(P), dim3(kBlock), 0, s, P, w, flow0, flow1, occ0, occ1);
   return hipGetLastError();
+}
+
+hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, int n, int total, size_t lds,
+                                 hipStream_t s) {
+  const dim3 grid(total, 2), block(kBlock);
+  switch (kind) {
+    case BK_RANSAC:
+      if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_ransac),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(kb_ransac, grid, block, lds, s, pd, it, n);
+      break;
+    case BK_ASSIGN:
+      hipLaunchKernelGGL(kb_assign, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_SYMMETRY:
+      hipLaunchKernelGGL(kb_symmetry, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_FB:
+      hipLaunchKernelGGL(kb_fb, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_COMMIT:
+      hipLaunchKernelGGL(kb_commit, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_NNF_UPDATE:
+      hipLaunchKernelGGL(kb_nnf_update, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_FINALIZE:
+      hipLaunchKernelGGL(kb_finalize, grid, block, 0, s, pd, it, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int pm_batch_blocks(int kind, const DevParams& P);
+
+int batch_grid_y(int kind) { return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE) ? 1 : 2; }
+
+int batch_blocks(int kind, const DevParams& P, const int* a) {
+  const int px = (P.W * P.H + kBlock - 1) / kBlock;
+  switch (kind) {
+    case BK_FEATURES:
+      return (P.W * P.H + 1 + kBlock - 1) / kBlock;
+    case BK_INIT_PLANES: {
+      const int np = 2 * P.planes_per_dir;
+      return ((np > kBlock ? np : kBlock) + kBlock - 1) / kBlock;
+    }
+    case BK_RANSAC:
+    case BK_SYMMETRY:
+      return P.nbx[a[0]] * P.nby[a[0]];
+    case BK_EVAL_COST_IDENT:
+    case BK_EVAL_COST_PLANE:
+    case BK_ZERO_ACTIVE:
+    case BK_ACTIVE_LIST:
+    case BK_PM_INIT:
+    case BK_PM_RESTRICTED:
+    case BK_PM_RESTRICTED_IDENT:
+      return pm_batch_blocks(kind, P);
+    default:
+      return px;
+  }
+}
+
+hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
+                          size_t lds, hipStream_t s) {
+  switch (kind) {
+    case BK_FEATURES:
+    case BK_INIT_PIXELS:
+    case BK_INIT_PLANES:
+      return launch_batched_init(kind, pd, it, n, total, s);
+    case BK_EVAL_COST_IDENT:
+    case BK_EVAL_COST_PLANE:
+    case BK_ZERO_ACTIVE:
+    case BK_ACTIVE_LIST:
+    case BK_PM_INIT:
+    case BK_PM_RESTRICTED:
+    case BK_PM_RESTRICTED_IDENT:
+      return launch_batched_pm(kind, P0, pd, it, n, total, s);
+    default:
+      return launch_batched_planes(kind, pd, it, n, total, lds, s);
+  }
 }
 
 }  // namespace msgpm

@@ -86,6 +86,10 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        L.msgpm_batch_query.argtypes = [i, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.msgpm_batch_query.restype = ctypes.c_int
+        L.msgpm_solve_batch.argtypes = [i, P] + [vp] * 11
+        L.msgpm_solve_batch.restype = ctypes.c_int
         L.msgpm_timing_enable.argtypes = [ctypes.c_int]
         L.msgpm_timing_enable.restype = ctypes.c_int
         L.msgpm_timing_read.argtypes = [vp, vp]
@@ -286,3 +290,46 @@ def solve(frame1, frame2, **params):
     pair = Pair(W, H, **params)
     flows, occs = pair.solve(frame1, frame2)
     return pair, flows, occs
+
+
+class Batch:
+    """Several frame pairs solved together (msgpm_solve_batch): one launch per
+    phase covers every pair.  pairs: Pair objects (their parameters and
+    workspaces); they must share patch radius, channels, storage, iteration
+    and level counts."""
+
+    def __init__(self, pairs):
+        self.pairs = list(pairs)
+        n = len(self.pairs)
+        self.params = (Params * n)(*[q.p for q in self.pairs])
+        nbytes = ctypes.c_uint64()
+        _call("msgpm_batch_query", n, self.params, ctypes.byref(nbytes))
+        dev = self.pairs[0].device
+        self.scratch = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        off = (-self.scratch.data_ptr()) % 256
+        self.scratch_ptr = ctypes.c_void_p(self.scratch.data_ptr() + off)
+        self.flows = [[torch.empty((q.H, q.W, 2), dtype=torch.float32, device=dev) for _ in range(2)]
+                      for q in self.pairs]
+        self.occs = [[torch.empty((q.H, q.W), dtype=torch.uint8, device=dev) for _ in range(2)] for q in self.pairs]
+
+    def solve(self, frames1, frames2, inits=None):
+        """Returns per pair ([flow0, flow1], [occ0, occ1]) as device tensors."""
+        n = len(self.pairs)
+        a = [q._frame(f) for q, f in zip(self.pairs, frames1)]
+        b = [q._frame(f) for q, f in zip(self.pairs, frames2)]
+        arr = lambda ts: (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
+        i0 = i1 = None
+        keep = [a, b]
+        if inits is not None:
+            t0 = [None if v is None or v[0] is None else torch.as_tensor(v[0]).to(q.device, torch.int32).contiguous()
+                  for q, v in zip(self.pairs, inits)]
+            t1 = [None if v is None or v[1] is None else torch.as_tensor(v[1]).to(q.device, torch.int32).contiguous()
+                  for q, v in zip(self.pairs, inits)]
+            i0, i1 = arr(t0), arr(t1)
+            keep += [t0, t1]
+        ws = arr([q.ws for q in self.pairs])
+        _call("msgpm_solve_batch", n, self.params, arr(a), arr(b), i0, i1, ws,
+              arr([f[0] for f in self.flows]), arr([f[1] for f in self.flows]),
+              arr([o[0] for o in self.occs]), arr([o[1] for o in self.occs]), self.scratch_ptr, _stream())
+        self._keep = keep
+        return list(zip(self.flows, self.occs))

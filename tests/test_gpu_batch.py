@@ -1,0 +1,76 @@
+"""Batched solves (msgpm_solve_batch): pairs of uneven sizes share one launch
+per phase, and each pair's outputs (flow, occlusion, plane table, NNF) are
+bit-identical to a msgpm_solve of that pair alone.  GPU against GPU: the
+single-pair path is held to the oracle by the parity tests."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1804_03787_amd import synth
+from tests.conftest import TINY_PARAMS
+from tests.test_gpu_parity import _gpu_params, _need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _outputs(g, flows, occs):
+    torch.cuda.synchronize()
+    return ([f.cpu().numpy() for f in flows], [o.cpu().numpy() for o in occs], g.planes(),
+            [g.nnf(d).cpu().numpy() for d in range(2)])
+
+
+def _same(a, b):
+    fa, oa, pa, na = a
+    fb, ob, pb, nb = b
+    for d in range(2):
+        assert np.array_equal(fa[d].view(np.uint32), fb[d].view(np.uint32))
+        assert np.array_equal(oa[d], ob[d])
+        assert np.array_equal(na[d], nb[d])
+    assert np.array_equal(pa.view(np.uint8), pb.view(np.uint8))
+
+
+def _run(msgpm, pairs, params, inits=None):
+    alone = []
+    for i, (pr, p) in enumerate(zip(pairs, params)):
+        H, W = pr.shape
+        g = msgpm.Pair(W, H, **p)
+        init = (None, None) if inits is None or inits[i] is None else inits[i]
+        flows, occs = g.solve(pr.frame1, pr.frame2, *init)
+        alone.append(_outputs(g, flows, occs))
+    gs = [msgpm.Pair(pr.shape[1], pr.shape[0], **p) for pr, p in zip(pairs, params)]
+    batch = msgpm.Batch(gs)
+    res = batch.solve([pr.frame1 for pr in pairs], [pr.frame2 for pr in pairs], inits)
+    for i, g in enumerate(gs):
+        _same(alone[i], _outputs(g, *res[i]))
+    return gs
+
+
+def test_batch_uneven_small_pairs_match_single_solves():
+    msgpm = _need_gpu()
+    pairs = [synth.tiny_pair(0), synth.planar_pair(160, 120, seed=3, scale=0.15),
+             synth.planar_pair(97, 61, seed=4, scale=0.1), synth.tiny_pair(0)]
+    base = _gpu_params(TINY_PARAMS)
+    params = [dict(base), dict(base, seed=5), dict(base, seed=6, blocks=(20,)), dict(base, fp16=False, seed=9)]
+    rng = np.random.default_rng(8)
+    H, W = pairs[1].shape
+    given = rng.integers(-40, 40, (2, H * W)).astype(np.int32)
+    inits = [None, (torch.from_numpy((given[0] & 0xffff) | (given[1] << 16)), None), None, None]
+    _run(msgpm, pairs, params, inits)
+
+
+def test_batch_paper_sizes_match_single_solves():
+    """Sizes of the batched workload (320x240 ... 1280x544), full parameters."""
+    msgpm = _need_gpu()
+    sizes = [(320, 240), (640, 360), (1024, 436), (1280, 544)]
+    pairs = [synth.planar_pair(W, H, seed=100 + i, scale=W / 1024) for i, (W, H) in enumerate(sizes)]
+    full = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0)
+    params = [_gpu_params(dict(full, seed=100 + i, fp16=True)) for i in range(len(sizes))]
+    _run(msgpm, pairs, params)
+
+
+def test_batch_rejects_mixed_shapes():
+    msgpm = _need_gpu()
+    base = _gpu_params(TINY_PARAMS)
+    gs = [msgpm.Pair(128, 96, **base), msgpm.Pair(128, 96, **dict(base, r=2))]
+    with pytest.raises(msgpm.MsgpmError):
+        msgpm.Batch(gs)
