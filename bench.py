@@ -75,6 +75,89 @@ def cpu_baseline(seconds_hint: float = 25.0) -> dict:
                       f"generator (lengths x1/8), same parameters, R0=1024; {dt:.1f} s"}
 
 
+BATCH_SIZES = [(320, 240), (640, 360), (1024, 436), (1280, 544)]
+
+
+def _batch_pair(i: int):
+    """Pair i of the batched workload: size uniform over BATCH_SIZES, 12-30
+    quads, displacements up to about 120 px (camera translation up to 40 px at
+    1024 width, lengths scaled with the width), occlusion by foreground quads
+    targeted uniformly in 3-8 %; scene seed 1000 + i."""
+    import numpy as np
+
+    from paper_1804_03787_amd import synth
+    rng = np.random.default_rng(1000 + i)
+    W, H = BATCH_SIZES[int(rng.integers(len(BATCH_SIZES)))]
+    occ = float(rng.uniform(0.03, 0.08))
+    pr = synth.planar_pair(W, H, seed=1000 + i, n_quads=int(rng.integers(12, 31)), cam_t=40.0,
+                           fg_occ=(occ - 0.005, occ + 0.005), scale=W / 1024)
+    return W, H, pr.frame1, pr.frame2
+
+
+def run_batched(args) -> int:
+    """Batched workload: n pairs of uneven sizes in one msgpm_solve_batch per
+    step (FP16 feature storage), against the same pairs solved one at a time in
+    the FP16 and the plain FP32 forms."""
+    import multiprocessing as mp
+
+    # scenes first, in worker processes started before this process touches the GPU
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        scenes = pool.map(_batch_pair, range(args.pairs))
+    print(f"bench: {args.pairs} scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1804_03787_amd import msgpm
+    msgpm.lib()
+    full = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0)
+    f1 = [torch.from_numpy(a).cuda() for _, _, a, _ in scenes]
+    f2 = [torch.from_numpy(b).cuda() for _, _, _, b in scenes]
+    mpix = sum(W * H for W, H, _, _ in scenes) / 1e6
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+
+    pairs16 = [msgpm.Pair(W, H, **dict(full, seed=1000 + i, fp16=True)) for i, (W, H, _, _) in enumerate(scenes)]
+    batch = msgpm.Batch(pairs16)
+    t_batch = timed(lambda: batch.solve(f1, f2))
+    print(f"bench: batched {t_batch * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_one16 = timed(lambda: [g.solve(a, b) for g, a, b in zip(pairs16, f1, f2)])
+    del batch, pairs16
+    pairs32 = [msgpm.Pair(W, H, **dict(full, seed=1000 + i)) for i, (W, H, _, _) in enumerate(scenes)]
+    t_one32 = timed(lambda: [g.solve(a, b) for g, a, b in zip(pairs32, f1, f2)])
+    line = {
+        "metric": "flow Mpix/s (batched, sum of W*H / makespan)",
+        "value": round(mpix / t_batch, 4),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.pairs} pairs, sizes uniform over 320x240/640x360/1024x436/1280x544, "
+                               "12-30 quads, 3-8% occlusion, patch 9x9, C=5, windows 64/32/16, 8 PM iterations, "
+                               "256 RANSAC hypotheses, FP16 feature storage",
+                   "pairs": args.pairs, "mpix_per_step": round(mpix, 4)},
+        "one_at_a_time_fp16_mpix_s": round(mpix / t_one16, 4),
+        "one_at_a_time_fp32_mpix_s": round(mpix / t_one32, 4),
+        "speedup_vs_fp32_one_at_a_time": round(t_one32 / t_batch, 3),
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +166,16 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
     ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
+    ap.add_argument("--batched", action="store_true",
+                    help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
+    ap.add_argument("--pairs", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not supported "
               "(pairs are independent, so more GPUs would run more pairs; see DESIGN.md)", file=sys.stderr)
         return 2
+    if args.batched:
+        return run_batched(args)
 
     import numpy as np
     import torch
