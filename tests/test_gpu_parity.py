@@ -56,6 +56,11 @@ CASES = {
     # FP16 feature storage with FP32 accumulation, against the oracle on the
     # same FP16-rounded features
     "tiny_c5_fp16": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fp16=True)),
+    # the paper's own preset: two levels of 81 and 41 pixel windows (strides 40
+    # and 20), 7x7 patches over RGB
+    "paper_preset": (lambda: synth.planar_pair(200, 144, seed=11, scale=0.08),
+                     dict(C=3, r=3, grad_weight=0.0, blocks=(81, 41), iters=4, hyps=128, tau=1.0, eps=0.1,
+                          tau_fb=1.0, seed=2)),
 }
 
 
