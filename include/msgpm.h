@@ -228,6 +228,34 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
                                void* d_scratch, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving: continuous batching of pairs that arrive at different times.  A
+ * server queues submitted pairs and admits them, first come first served,
+ * while the sum of the admitted pairs' workspace bytes stays within
+ * hbm_budget and at most max_active are in flight.  Each msgpm_server_step
+ * issues one scheduling round on `stream`: the in-flight pairs are grouped by
+ * the kind of their next pipeline step and every group becomes one batched
+ * launch (pairs at different iterations, levels or stages share it), after
+ * which each pair has advanced by one step.  A pair's results (as msgpm_solve,
+ * and identical to them) are complete once msgpm_server_poll reports it done;
+ * its ticket is then retired.  All pairs of a server share patch_radius,
+ * channels and the FP16 flag.  Buffers are caller-owned and must stay valid
+ * until the pair is done; d_scratch (msgpm_server_scratch_bytes for
+ * max_active, 256-byte aligned) holds each round's launch tables.  One host
+ * thread at a time per server (calls are serialised by a lock).
+ * ------------------------------------------------------------------------- */
+typedef struct msgpm_server msgpm_server;
+msgpm_status msgpm_server_create(uint64_t hbm_budget, int max_active, msgpm_server** out);
+msgpm_status msgpm_server_destroy(msgpm_server* server);
+msgpm_status msgpm_server_scratch_bytes(int max_active, uint64_t* bytes);
+msgpm_status msgpm_server_submit(msgpm_server* server, const msgpm_params* p, const float* d_rgb1,
+                                 const float* d_rgb2, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
+                                 void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1,
+                                 uint64_t* ticket);
+/* *pending: pairs queued or still being launched after this round. */
+msgpm_status msgpm_server_step(msgpm_server* server, void* d_scratch, void* stream, int* pending);
+msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing.  While enabled, the library records a pair of HIP events on
  * the launch stream around every kernel it launches (from any entry point) and
  * attributes the elapsed time to one of the kinds below.  msgpm_timing_read

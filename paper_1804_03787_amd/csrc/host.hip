@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -601,6 +603,281 @@ msgpm_status msgpm_timing_read(double* ms, int64_t* launches) {
   for (int k = 0; k < MSGPM_TIMER_KINDS; ++k) {
     if (ms) ms[k] = t[k];
     if (launches) launches[k] = n[k];
+  }
+  return MSGPM_OK;
+}
+
+}  // extern "C"
+
+// ---- serving: continuous batching of pairs at different steps ----------------
+namespace {
+
+struct Slot {
+  uint64_t ticket = 0;
+  DevParams P;
+  PairDesc desc;
+  std::vector<BatchStep> steps;
+  size_t cursor = 0;
+  uint64_t bytes = 0;           // workspace footprint counted against the budget
+  hipEvent_t done = nullptr;    // recorded after the pair's last launch
+  int state = 0;                // 0 queued, 1 active, 2 all launched, 3 finished
+};
+
+}  // namespace
+
+struct msgpm_server {
+  std::mutex mu;
+  uint64_t budget = 0;
+  int max_active = 0;
+  uint64_t next_ticket = 1;
+  uint64_t in_use = 0;
+  bool shape_set = false;
+  int r = 0, C = 0, fp16 = 0;
+  std::deque<Slot*> queue;
+  std::vector<Slot*> active;
+  std::map<uint64_t, Slot*> slots;
+  std::vector<hipEvent_t> events;  // completion events to reuse
+  void* host[2] = {nullptr, nullptr};
+  size_t cap[2] = {0, 0};
+  hipEvent_t up[2] = {nullptr, nullptr};
+  int ring = 0;
+};
+
+namespace {
+
+uint64_t server_scratch(int max_active) {
+  return align256((uint64_t)max_active * sizeof(PairDesc)) + align256((uint64_t)max_active * sizeof(Item));
+}
+
+// Marks launched pairs whose completion event has passed as finished and
+// releases their budget.
+void server_retire(msgpm_server* sv) {
+  for (auto& kv : sv->slots) {
+    Slot* q = kv.second;
+    if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
+      q->state = 3;
+      sv->in_use -= q->bytes;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+msgpm_status msgpm_server_create(uint64_t hbm_budget, int max_active, msgpm_server** out) {
+  if (!out) return fail(MSGPM_E_INVALID, "out is NULL");
+  if (max_active < 1 || max_active > 4096) return fail(MSGPM_E_INVALID, "max_active outside 1..4096");
+  msgpm_server* sv = new msgpm_server;
+  sv->budget = hbm_budget;
+  sv->max_active = max_active;
+  *out = sv;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_destroy(msgpm_server* sv) {
+  if (!sv) return MSGPM_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (auto& kv : sv->slots) {
+      if (kv.second->done) {
+        (void)hipEventSynchronize(kv.second->done);
+        (void)hipEventDestroy(kv.second->done);
+      }
+      delete kv.second;
+    }
+    for (hipEvent_t e : sv->events) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k) {
+      if (sv->up[k]) {
+        (void)hipEventSynchronize(sv->up[k]);
+        (void)hipEventDestroy(sv->up[k]);
+      }
+      if (sv->host[k]) (void)hipHostFree(sv->host[k]);
+    }
+  }
+  delete sv;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_scratch_bytes(int max_active, uint64_t* bytes) {
+  if (!bytes || max_active < 1) return fail(MSGPM_E_INVALID, "bad arguments");
+  *bytes = server_scratch(max_active);
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_submit(msgpm_server* sv, const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                                 const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws,
+                                 float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1,
+                                 uint64_t* ticket) {
+  if (!sv || !ticket) return fail(MSGPM_E_INVALID, "server or ticket is NULL");
+  Slot* q = new Slot;
+  msgpm_layout L;
+  msgpm_status st = prepare(p, &q->P, &L);
+  if (st != MSGPM_OK) {
+    delete q;
+    return st;
+  }
+  if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255) || !d_rgb1 || !d_rgb2 || !d_flow0 || !d_flow1 || !d_occ0 ||
+      !d_occ1) {
+    delete q;
+    return fail(MSGPM_E_INVALID, "NULL or misaligned buffer");
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (!sv->shape_set) {
+    sv->r = q->P.r;
+    sv->C = q->P.C;
+    sv->fp16 = q->P.fp16;
+    sv->shape_set = true;
+  } else if (q->P.r != sv->r || q->P.C != sv->C || q->P.fp16 != sv->fp16) {
+    delete q;
+    return fail(MSGPM_E_INVALID, "a server serves one patch radius, channel count and storage");
+  }
+  q->bytes = L.total_bytes;
+  if (q->bytes > sv->budget) {
+    delete q;
+    return fail(MSGPM_E_INVALID, "workspace of %llu bytes exceeds the budget", (unsigned long long)L.total_bytes);
+  }
+  memset(&q->desc, 0, sizeof q->desc);
+  q->desc.P = q->P;
+  q->desc.w = make_ws(q->P, L, d_ws);
+  q->desc.rgb[0] = d_rgb1;
+  q->desc.rgb[1] = d_rgb2;
+  q->desc.init[0] = d_init_nnf0;
+  q->desc.init[1] = d_init_nnf1;
+  q->desc.flow[0] = d_flow0;
+  q->desc.flow[1] = d_flow1;
+  q->desc.occ[0] = d_occ0;
+  q->desc.occ[1] = d_occ1;
+  q->steps = batch_schedule(q->P);
+  q->ticket = sv->next_ticket++;
+  sv->queue.push_back(q);
+  sv->slots[q->ticket] = q;
+  *ticket = q->ticket;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, int* pending) {
+  if (!sv || !d_scratch || (reinterpret_cast<uintptr_t>(d_scratch) & 255))
+    return fail(MSGPM_E_INVALID, "server NULL or scratch NULL / misaligned");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  msgpm_status st;
+  server_retire(sv);
+  // admission: first come, first served, while the budget and the slot count allow
+  while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
+         sv->in_use + sv->queue.front()->bytes <= sv->budget) {
+    Slot* q = sv->queue.front();
+    sv->queue.pop_front();
+    q->state = 1;
+    sv->in_use += q->bytes;
+    sv->active.push_back(q);
+  }
+  const int n = (int)sv->active.size();
+  if (pending) *pending = n + (int)sv->queue.size();
+  if (n == 0) return MSGPM_OK;
+  // group the active pairs by the kind of their next step; one launch per kind
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return sv->active[a]->steps[sv->active[a]->cursor].kind < sv->active[b]->steps[sv->active[b]->cursor].kind;
+  });
+  const uint64_t desc_bytes = align256((uint64_t)n * sizeof(PairDesc));
+  const uint64_t bytes = desc_bytes + (uint64_t)n * sizeof(Item);
+  struct Group {
+    int kind, first, count, total;
+    size_t lds;
+  };
+  std::vector<Group> groups;
+  std::vector<Item> items(n);
+  for (int k = 0; k < n;) {
+    const int kind = sv->active[order[k]]->steps[sv->active[order[k]]->cursor].kind;
+    Group gr{kind, k, 0, 0, 0};
+    int start = 0;
+    for (; k < n && sv->active[order[k]]->steps[sv->active[order[k]]->cursor].kind == kind; ++k) {
+      Slot* q = sv->active[order[k]];
+      const BatchStep& bs = q->steps[q->cursor];
+      Item& it = items[k];
+      memset(&it, 0, sizeof it);
+      it.pair = order[k];
+      it.nb = batch_blocks(kind, q->P, bs.a);
+      it.start = kind == BK_ZERO_ACTIVE ? gr.count : start;
+      for (int a = 0; a < 5; ++a) it.a[a] = bs.a[a];
+      start += (it.nb + kXcds - 1) / kXcds * kXcds;
+      if (kind == BK_RANSAC) {
+        const size_t m = ransac_smem_bytes(q->P, bs.a[0]);
+        gr.lds = m > gr.lds ? m : gr.lds;
+      }
+      ++gr.count;
+    }
+    gr.total = kind == BK_ZERO_ACTIVE ? gr.count : start;
+    groups.push_back(gr);
+  }
+  // upload through the staging ring (the slot's previous upload has completed)
+  const int r = sv->ring;
+  sv->ring ^= 1;
+  if (sv->up[r] && (st = check(hipEventSynchronize(sv->up[r]), "staging")) != MSGPM_OK) return st;
+  if (sv->cap[r] < bytes) {
+    if (sv->host[r]) (void)hipHostFree(sv->host[r]);
+    sv->host[r] = nullptr;
+    sv->cap[r] = 0;
+    const size_t want = server_scratch(sv->max_active);
+    if ((st = check(hipHostMalloc(&sv->host[r], want, hipHostMallocDefault), "staging")) != MSGPM_OK) return st;
+    sv->cap[r] = want;
+  }
+  if (!sv->up[r] && (st = check(hipEventCreateWithFlags(&sv->up[r], hipEventDisableTiming), "staging")) != MSGPM_OK)
+    return st;
+  char* h = static_cast<char*>(sv->host[r]);
+  for (int i = 0; i < n; ++i) memcpy(h + (size_t)i * sizeof(PairDesc), &sv->active[i]->desc, sizeof(PairDesc));
+  memcpy(h + desc_bytes, items.data(), (size_t)n * sizeof(Item));
+  char* dev = static_cast<char*>(d_scratch);
+  if ((st = check(hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, s), "upload")) != MSGPM_OK) return st;
+  if ((st = check(hipEventRecord(sv->up[r], s), "staging")) != MSGPM_OK) return st;
+  const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
+  const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
+  DevParams P0 = sv->active[0]->P;
+  for (const Group& gr : groups) {
+    const BatchStep& bs = sv->active[order[gr.first]]->steps[sv->active[order[gr.first]]->cursor];
+    st = check(timed(bs.timer, s, [&] { return launch_batched(gr.kind, P0, pd, it + gr.first, gr.count, gr.total, gr.lds, s); }),
+               "batched launch");
+    if (st != MSGPM_OK) return st;
+  }
+  // advance; pairs whose last step was launched get their completion event
+  std::vector<Slot*> still;
+  for (Slot* q : sv->active) {
+    if (++q->cursor < q->steps.size()) {
+      still.push_back(q);
+      continue;
+    }
+    if (sv->events.empty()) {
+      hipEvent_t e;
+      if ((st = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != MSGPM_OK) return st;
+      sv->events.push_back(e);
+    }
+    q->done = sv->events.back();
+    sv->events.pop_back();
+    if ((st = check(hipEventRecord(q->done, s), "event")) != MSGPM_OK) return st;
+    q->state = 2;
+  }
+  sv->active.swap(still);
+  if (pending) *pending = (int)(sv->active.size() + sv->queue.size());
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_poll(msgpm_server* sv, uint64_t ticket, int* done) {
+  if (!sv || !done) return fail(MSGPM_E_INVALID, "server or done is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto f = sv->slots.find(ticket);
+  if (f == sv->slots.end()) return fail(MSGPM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Slot* q = f->second;
+  if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
+    q->state = 3;
+    sv->in_use -= q->bytes;
+  }
+  *done = q->state == 3;
+  if (*done) {
+    sv->events.push_back(q->done);
+    sv->slots.erase(f);
+    delete q;
   }
   return MSGPM_OK;
 }

@@ -90,6 +90,17 @@ def lib() -> ctypes.CDLL:
         L.msgpm_batch_query.restype = ctypes.c_int
         L.msgpm_solve_batch.argtypes = [i, P] + [vp] * 11
         L.msgpm_solve_batch.restype = ctypes.c_int
+        u64, pu64 = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)
+        for name, args in {
+            "msgpm_server_create": [u64, i, ctypes.POINTER(vp)],
+            "msgpm_server_destroy": [vp],
+            "msgpm_server_scratch_bytes": [i, pu64],
+            "msgpm_server_submit": [vp, P] + [vp] * 9 + [pu64],
+            "msgpm_server_step": [vp, vp, vp, ctypes.POINTER(i)],
+            "msgpm_server_poll": [vp, u64, ctypes.POINTER(i)],
+        }.items():
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = ctypes.c_int
         L.msgpm_timing_enable.argtypes = [ctypes.c_int]
         L.msgpm_timing_enable.restype = ctypes.c_int
         L.msgpm_timing_read.argtypes = [vp, vp]
@@ -333,3 +344,58 @@ class Batch:
               arr([o[0] for o in self.occs]), arr([o[1] for o in self.occs]), self.scratch_ptr, _stream())
         self._keep = keep
         return list(zip(self.flows, self.occs))
+
+
+class Server:
+    """Continuous batching (msgpm_server_*): pairs submitted at any time are
+    admitted within an HBM budget and advanced one pipeline step per round,
+    pairs at the same kind of step sharing one launch."""
+
+    def __init__(self, hbm_budget: int, max_active: int, device="cuda"):
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        _call("msgpm_server_create", int(hbm_budget), int(max_active), ctypes.byref(h))
+        self.h = h
+        nbytes = ctypes.c_uint64()
+        _call("msgpm_server_scratch_bytes", int(max_active), ctypes.byref(nbytes))
+        self.scratch = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        self.scratch_ptr = ctypes.c_void_p(self.scratch.data_ptr() + (-self.scratch.data_ptr()) % 256)
+        self.jobs = {}
+
+    def submit(self, pair: "Pair", rgb1, rgb2, init0=None, init1=None) -> int:
+        a, b = pair._frame(rgb1), pair._frame(rgb2)
+        i0 = None if init0 is None else torch.as_tensor(init0).to(self.device, torch.int32).contiguous()
+        i1 = None if init1 is None else torch.as_tensor(init1).to(self.device, torch.int32).contiguous()
+        flows = [torch.empty((pair.H, pair.W, 2), dtype=torch.float32, device=self.device) for _ in range(2)]
+        occs = [torch.empty((pair.H, pair.W), dtype=torch.uint8, device=self.device) for _ in range(2)]
+        t = ctypes.c_uint64()
+        _call("msgpm_server_submit", self.h, ctypes.byref(pair.p), _ptr(a), _ptr(b), _ptr(i0), _ptr(i1),
+              _ptr(pair.ws), _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), ctypes.byref(t))
+        self.jobs[t.value] = (pair, flows, occs, (a, b, i0, i1))
+        return t.value
+
+    def step(self) -> int:
+        n = ctypes.c_int()
+        _call("msgpm_server_step", self.h, self.scratch_ptr, _stream(), ctypes.byref(n))
+        return n.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _call("msgpm_server_poll", self.h, int(ticket), ctypes.byref(d))
+        return bool(d.value)
+
+    def result(self, ticket: int):
+        """(pair, [flow0, flow1], [occ0, occ1]) of a finished ticket; forgets it."""
+        pair, flows, occs, _ = self.jobs.pop(ticket)
+        return pair, flows, occs
+
+    def close(self):
+        if self.h:
+            _call("msgpm_server_destroy", self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
