@@ -158,6 +158,148 @@ def run_batched(args) -> int:
     return 0
 
 
+SERVE_SIZES = [((1024, 436), 0.5, (64, 32, 16)), ((640, 360), 0.3, (64, 32, 16)),
+               ((2048, 872), 0.2, (128, 64, 32, 16))]
+SERVE_SCENES = [6, 4, 3]  # distinct scenes per size class
+
+
+def _serve_scene(job):
+    """Scene j of size class c of the serving workload (seed 2000 + 100 c + j)."""
+    from paper_1804_03787_amd import synth
+    c, j = job
+    (W, H), _, _ = SERVE_SIZES[c]
+    pr = synth.planar_pair(W, H, seed=2000 + 100 * c + j, scale=W / 1024)
+    return c, j, pr.frame1, pr.frame2
+
+
+def run_serving(args) -> int:
+    """Serving workload: Poisson arrivals, sizes 50 % 1024x436, 30 % 640x360,
+    20 % 2048x872 (4 window scales), FP16 feature storage, continuous batching
+    (msgpm_server_*).  First the capacity (every request submitted at once),
+    then the arrival trace at --rate and at 60 % of the capacity, then the
+    same trace served one pair at a time in the plain FP32 form.  Frames come
+    from a pool of distinct scenes per size class (every request is solved in
+    full; nothing is cached between requests)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    t0 = time.perf_counter()
+    jobs = [(c, j) for c, k in enumerate(SERVE_SCENES) for j in range(k)]
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        scenes = pool.map(_serve_scene, jobs)
+    print(f"bench: {len(scenes)} scenes generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1804_03787_amd import msgpm
+    msgpm.lib()
+    frames = {(c, j): (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for c, j, a, b in scenes}
+    full = dict(C=5, r=4, iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0)
+
+    def trace(rate, duration, seed):
+        rng = np.random.default_rng(seed)
+        t, out = 0.0, []
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t > duration:
+                return out
+            c = int(rng.choice(len(SERVE_SIZES), p=[w for _, w, _ in SERVE_SIZES]))
+            out.append((t, c, int(rng.integers(SERVE_SCENES[c]))))
+
+    def make_pair(c, fp16):
+        (W, H), _, blocks = SERVE_SIZES[c]
+        return msgpm.Pair(W, H, **dict(full, blocks=blocks, fp16=fp16))
+
+    def serve(reqs, max_active=64, budget=200 << 30):
+        """Returns (latencies in s, makespan in s, Mpix)."""
+        srv = msgpm.Server(budget, max_active)
+        lat, out = [], {}
+        mpix = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] for _, c, _ in reqs) / 1e6
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        k = 0
+        while k < len(reqs) or out:
+            now = time.perf_counter() - start
+            while k < len(reqs) and reqs[k][0] <= now:
+                t, c, j = reqs[k]
+                a, b = frames[(c, j)]
+                out[srv.submit(make_pair(c, True), a, b)] = t
+                k += 1
+            if out:
+                srv.step()
+                now = time.perf_counter() - start
+                for tk in [tk for tk in out if srv.poll(tk)]:
+                    lat.append(now - out.pop(tk))
+                    srv.result(tk)
+            elif k < len(reqs):
+                time.sleep(max(0.0, reqs[k][0] - (time.perf_counter() - start)))
+        span = time.perf_counter() - start
+        srv.close()
+        return np.array(lat), span, mpix
+
+    def one_at_a_time(reqs):
+        pairs = {c: make_pair(c, False) for c in range(len(SERVE_SIZES))}
+        lat = []
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for t, c, j in reqs:
+            now = time.perf_counter() - start
+            if now < t:
+                time.sleep(t - now)
+            a, b = frames[(c, j)]
+            pairs[c].solve(a, b)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - start - t)
+        return np.array(lat), time.perf_counter() - start
+
+    # capacity: every request of a trace submitted at time 0
+    cap_reqs = [(0.0, c, j) for _, c, j in trace(args.rate, args.duration / 2, 4)]
+    serve(cap_reqs[:8])  # warm-up
+    _, span, mpix = serve(cap_reqs)
+    capacity = mpix / span
+    print(f"bench: capacity {capacity:.2f} Mpix/s ({len(cap_reqs)} pairs in {span:.2f} s)", file=sys.stderr,
+          flush=True)
+    mean_mpix = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] * w for c, (_, w, _) in enumerate(SERVE_SIZES)) / 1e6
+    runs = {}
+    for label, rate in (("offered", args.rate), ("stable", 0.6 * capacity / mean_mpix)):
+        reqs = trace(rate, args.duration, 4)
+        lat, span, mpix = serve(reqs)
+        offered = rate * mean_mpix
+        runs[label] = {"rate_pairs_s": round(rate, 2), "offered_mpix_s": round(offered, 2), "pairs": len(reqs),
+                       "throughput_mpix_s": round(mpix / span, 3), "p50_ms": round(float(np.median(lat)) * 1e3, 1),
+                       "p99_ms": round(float(np.quantile(lat, 0.99)) * 1e3, 1),
+                       "queue_stable": bool(offered < capacity)}
+        print(f"bench: {label} {runs[label]}", file=sys.stderr, flush=True)
+    reqs = trace(runs["stable"]["rate_pairs_s"], args.duration, 4)
+    lat1, span1 = one_at_a_time(reqs)
+    mpix1 = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] for _, c, _ in reqs) / 1e6
+    runs["stable_one_at_a_time_fp32"] = {"throughput_mpix_s": round(mpix1 / span1, 3),
+                                         "p50_ms": round(float(np.median(lat1)) * 1e3, 1),
+                                         "p99_ms": round(float(np.quantile(lat1, 0.99)) * 1e3, 1)}
+    line = {
+        "metric": "serving: flow Mpix/s and p50/p99 pair latency",
+        "value": runs["stable"]["throughput_mpix_s"],
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": "Poisson arrivals; sizes 50% 1024x436, 30% 640x360, 20% 2048x872 (windows "
+                               "128/64/32/16); patch 9x9, C=5, 8 PM iterations, 256 RANSAC hypotheses; FP16 "
+                               "storage; continuous batching",
+                   "duration_s": args.duration},
+        "capacity_mpix_s": round(capacity, 3),
+        "runs": runs,
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +311,9 @@ def main() -> int:
     ap.add_argument("--batched", action="store_true",
                     help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
     ap.add_argument("--pairs", type=int, default=48)
+    ap.add_argument("--serving", action="store_true", help="serving workload: Poisson arrivals, continuous batching")
+    ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not supported "
@@ -176,6 +321,8 @@ def main() -> int:
         return 2
     if args.batched:
         return run_batched(args)
+    if args.serving:
+        return run_serving(args)
 
     import numpy as np
     import torch
