@@ -12,9 +12,15 @@ the MPI-Sintel frames of the paper's experiments; 9x9 patches over RGB + luma
 gradients, windows 64/32/16, 8 PatchMatch iterations per pass, 256 RANSAC
 hypotheses per window, FP32 patch costs, FP64 plane fits.
 
-Prints one JSON line: flow Mpix/s, the dominant kernel's roofline (timed with
-HIP events around each launch inside the timed region) and the FP64 CPU oracle
-timed on a bounded sample on this host.
+Prints one JSON line: flow Mpix/s of the timed steps (each step one launch of
+the pipeline captured as a HIP graph, msgpm_solve_graph; --no-graph: eager
+launches), the dominant kernel's roofline (from an equal number of eager steps
+timed with HIP events around each launch) and the FP64 CPU oracle timed on a
+bounded sample on this host.
+
+Other workloads: --fp16 (FP16 feature storage), --seed, --batched (uneven
+pairs per msgpm_solve_batch), --serving (Poisson arrivals, continuous
+batching).
 """
 from __future__ import annotations
 
@@ -39,7 +45,7 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 TRAFFIC = {
     # profiles/k_pm_halfsweep_1024x436_traffic.md
     "k_pm_halfsweep (identity patches)": 1.548e9,
-    "k_pm_halfsweep (distorted patches)": 3.499e8,
+    "k_pm_halfsweep (distorted patches)": 3.483e8,
 }
 
 
@@ -306,6 +312,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches only (default: the pipeline as one captured HIP graph per step, "
+                         "plus an eager pass with HIP events around every launch for the per-kernel figures)")
     ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
     ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
     ap.add_argument("--batched", action="store_true",
@@ -337,8 +346,11 @@ def main() -> int:
     g = msgpm.Pair(W, H, **params)
     flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
     occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    use_graph = not args.no_graph
     for _ in range(args.warmup):
         g.solve(f1, f2, out=(flows, occs))
+        if use_graph:
+            g.solve(f1, f2, out=(flows, occs), graph=True)
     torch.cuda.synchronize()
     print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
@@ -352,9 +364,20 @@ def main() -> int:
     t1 = time.perf_counter()
     timing = msgpm.timing_read()
     msgpm.timing_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    eager_ms = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = eager_ms
+    if use_graph:
+        # the timed steps: the same pipeline launched as one captured HIP graph each
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            g.solve(f1, f2, out=(flows, occs), graph=True)
+        torch.cuda.synchronize()
+        ms_per_step = (time.perf_counter() - tg) * 1e3 / args.steps
+        print(f"bench: eager {eager_ms:.2f} ms/step, graph {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+    print(f"bench: timed {args.steps} eager steps with per-launch events", file=sys.stderr, flush=True)
+
     value = W * H / (ms_per_step / 1e3) / 1e6
-    print(f"bench: timed {args.steps} steps, {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
 
     # evaluations of the last step (every step is identical: same inputs and seed);
     # a candidate rejected early by its partial sum counts for the rows it computed
@@ -414,6 +437,8 @@ def main() -> int:
         "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in kernel_ms.items()},
         "occluded_fraction_dir0": round(occ0, 4),
+        "launch": "hip graph per step" if use_graph else "eager",
+        "eager_ms_per_step": round(eager_ms, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -201,6 +201,19 @@ msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void
 msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
                             uint8_t* d_occ1, void* stream);
 
+/* msgpm_solve through a HIP graph: the first call with a given parameter set
+ * and set of buffer addresses captures the whole launch sequence (on a stream
+ * of the library's) into a graph; every call launches that graph on `stream`,
+ * so the pipeline's ~200 launches cost one.  Results are identical to
+ * msgpm_solve.  Up to 16 graphs are kept (oldest dropped); kernel timing does
+ * not see graph launches.  msgpm_graph_cache_clear drops them all (call it
+ * before freeing buffers a cached graph refers to, if the addresses may be
+ * reused with other contents and the same parameters). */
+msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                               const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws,
+                               float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream);
+msgpm_status msgpm_graph_cache_clear(void);
+
 /* ---------------------------------------------------------------------------
  * Batched solves: the pipeline of msgpm_solve for n frame pairs at once, one
  * launch per phase covering every pair (pairs of different sizes share the

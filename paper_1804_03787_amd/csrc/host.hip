@@ -18,6 +18,7 @@ using namespace msgpm;
 namespace {
 
 thread_local std::string g_err;
+thread_local bool g_capturing = false;  // launches are being captured into a graph: no timing events
 
 msgpm_status fail(msgpm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 msgpm_status fail(msgpm_status s, const char* fmt, ...) {
@@ -68,7 +69,7 @@ Timer g_timer;
 
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
-  if (!g_timer.on) return launch();
+  if (!g_timer.on || g_capturing) return launch();
   std::lock_guard<std::mutex> lk(g_timer.mu);
   hipEvent_t a = g_timer.get(), b = g_timer.get();
   if (!a || !b) return hipErrorOutOfMemory;
@@ -346,13 +347,14 @@ msgpm_status msgpm_finalize(const msgpm_params* p, void* d_ws, float* d_flow0, f
   return check(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 }
 
-msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
-                         const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws, float* d_flow0,
-                         float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream) {
-  Ctx c;
-  msgpm_status st = open_ctx(p, d_ws, stream, &c);
-  if (st != MSGPM_OK) return st;
-  if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
+}  // extern "C"
+
+namespace {
+
+msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rgb2, const int32_t* d_init_nnf0,
+                            const int32_t* d_init_nnf1, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
+                            uint8_t* d_occ1) {
+  msgpm_status st;
 #define RUN(expr, what)                          \
   do {                                           \
     msgpm_status s_ = check((expr), what);       \
@@ -378,6 +380,80 @@ msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float
   RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 2, c.s); }), "eval_cost");
   RUN(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 #undef RUN
+  return MSGPM_OK;
+}
+
+// Instantiated graphs of whole pipelines, keyed by the parameters and every
+// buffer address; the oldest is dropped beyond kGraphCache.
+constexpr size_t kGraphCache = 16;
+struct GraphCache {
+  std::mutex mu;
+  std::vector<std::pair<std::string, hipGraphExec_t>> entries;
+  hipStream_t capture = nullptr;
+};
+GraphCache g_graphs;
+
+}  // namespace
+
+extern "C" {
+
+msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                         const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws, float* d_flow0,
+                         float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
+  return solve_sequence(c, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_flow0, d_flow1, d_occ0, d_occ1);
+}
+
+msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                               const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws,
+                               float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
+  const void* ptrs[] = {d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_ws, d_flow0, d_flow1, d_occ0, d_occ1};
+  std::string key(reinterpret_cast<const char*>(p), sizeof *p);
+  key.append(reinterpret_cast<const char*>(ptrs), sizeof ptrs);
+  std::lock_guard<std::mutex> lk(g_graphs.mu);
+  hipGraphExec_t exec = nullptr;
+  for (auto& e : g_graphs.entries)
+    if (e.first == key) exec = e.second;
+  if (!exec) {
+    if (!g_graphs.capture &&
+        (st = check(hipStreamCreateWithFlags(&g_graphs.capture, hipStreamNonBlocking), "graph stream")) != MSGPM_OK)
+      return st;
+    Ctx cc = c;
+    cc.s = g_graphs.capture;
+    if ((st = check(hipStreamBeginCapture(cc.s, hipStreamCaptureModeThreadLocal), "graph capture")) != MSGPM_OK)
+      return st;
+    g_capturing = true;
+    msgpm_status run = solve_sequence(cc, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_flow0, d_flow1, d_occ0, d_occ1);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    st = check(hipStreamEndCapture(cc.s, &graph), "graph capture");
+    if (run != MSGPM_OK || st != MSGPM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return run != MSGPM_OK ? run : st;
+    }
+    st = check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    if (st != MSGPM_OK) return st;
+    if (g_graphs.entries.size() >= kGraphCache) {
+      (void)hipGraphExecDestroy(g_graphs.entries.front().second);
+      g_graphs.entries.erase(g_graphs.entries.begin());
+    }
+    g_graphs.entries.emplace_back(key, exec);
+  }
+  return check(hipGraphLaunch(exec, c.s), "graph launch");
+}
+
+msgpm_status msgpm_graph_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_graphs.mu);
+  for (auto& e : g_graphs.entries) (void)hipGraphExecDestroy(e.second);
+  g_graphs.entries.clear();
   return MSGPM_OK;
 }
 

@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         sigs = {
             "msgpm_layout_query": [P, ctypes.POINTER(Layout)],
             "msgpm_solve": [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "msgpm_solve_graph": [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "msgpm_features": [P, vp, vp, vp, vp],
             "msgpm_init_state": [P, vp, vp, vp, vp],
             "msgpm_eval_cost": [P, vp, i, vp],
@@ -101,6 +102,8 @@ def lib() -> ctypes.CDLL:
         }.items():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = ctypes.c_int
+        L.msgpm_graph_cache_clear.argtypes = []
+        L.msgpm_graph_cache_clear.restype = ctypes.c_int
         L.msgpm_timing_enable.argtypes = [ctypes.c_int]
         L.msgpm_timing_enable.restype = ctypes.c_int
         L.msgpm_timing_read.argtypes = [vp, vp]
@@ -279,8 +282,11 @@ class Pair:
               _ptr(occs[0]), _ptr(occs[1]), _stream())
         return flows, occs
 
-    def solve(self, rgb1, rgb2, init0=None, init1=None, out=None):
-        """Whole pipeline; returns ([flow0, flow1], [occ0, occ1]) as device tensors."""
+    def solve(self, rgb1, rgb2, init0=None, init1=None, out=None, graph=False):
+        """Whole pipeline; returns ([flow0, flow1], [occ0, occ1]) as device tensors.
+        graph: launch through a cached HIP graph of the whole sequence
+        (msgpm_solve_graph; the frames, initial NNF and outputs must then be the
+        same device buffers on every call for the cache to hit)."""
         a, b = self._frame(rgb1), self._frame(rgb2)
         i0 = None if init0 is None else torch.as_tensor(init0).to(self.device, torch.int32).contiguous()
         i1 = None if init1 is None else torch.as_tensor(init1).to(self.device, torch.int32).contiguous()
@@ -289,7 +295,8 @@ class Pair:
             occs = [torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device) for _ in range(2)]
         else:
             flows, occs = out
-        _call("msgpm_solve", ctypes.byref(self.p), _ptr(a), _ptr(b), _ptr(i0), _ptr(i1), _ptr(self.ws),
+        _call("msgpm_solve_graph" if graph else "msgpm_solve", ctypes.byref(self.p), _ptr(a), _ptr(b), _ptr(i0),
+              _ptr(i1), _ptr(self.ws),
               _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _stream())
         self._keep = (a, b, i0, i1)
         return flows, occs
