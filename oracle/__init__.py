@@ -17,14 +17,16 @@ SRC = os.path.join(_HERE, "msgpm_oracle.c")
 LIB = os.path.join(_HERE, "libmsgpm_oracle.so")
 
 PI_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "support", "count", "hyp",
-             "hyp_count", "refit", "detected", "rk", "pass", "valid"]
+             "hyp_count", "refit", "detected", "rk", "pass", "valid", "rin"]
 PI = {n: i for i, n in enumerate(PI_FIELDS)}
 
 F_COST, F_ROUND, F_COLOUR, F_FB, F_BOUNDS, F_RANSAC = 1, 2, 4, 8, 16, 32
 B_RCOUNT, B_SYMCOUNT = 64, 128
 
 DEFAULTS = dict(C=5, r=4, grad_weight=1.0, blocks=(64, 32, 16), iters=8, hyps=256, R0=0, tau=1.0, eps=0.1,
-                tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False)
+                tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False, cue_overlap=False,
+                cue_unique=False)
+CUE_OVERLAP, CUE_UNIQUE = 1, 2
 
 
 def build(verbose: bool = False) -> str:
@@ -74,6 +76,7 @@ def lib():
             "orc_symmetry": (None, [P, i, i]),
             "orc_fb_test": (i, [P, i, i, i, vp, vp, vp]),
             "orc_fb_unassign": (None, [P]),
+            "orc_unique": (None, [P]),
             "orc_nnf_update": (None, [P, i, i]),
             "orc_finalize": (None, [P, i, vp, vp]),
             "orc_solve": (None, [P, vp, vp, vp, vp, vp, vp]),
@@ -100,7 +103,7 @@ class _Pair(ctypes.Structure):
         ("loss", ctypes.c_void_p * 2), ("hlabel", ctypes.c_void_p * 2), ("twin", ctypes.c_void_p * 2),
         ("tloss", ctypes.c_void_p * 2), ("pflag", ctypes.c_void_p * 2),
         ("P", ctypes.c_int32), ("pH", ctypes.c_void_p), ("pinfo", ctypes.c_void_p), ("bflag", ctypes.c_void_p),
-        ("evals", ctypes.c_int64),
+        ("evals", ctypes.c_int64), ("cues", ctypes.c_int32),
     ]
 
 
@@ -206,6 +209,7 @@ class Oracle:
         s.eta_num, s.eta_den = p["eta"]
         s.tau, s.eps, s.tau_fb, s.mu = p["tau"], p["eps"], p["tau_fb"], p["mu"]
         s.seed = p["seed"]
+        s.cues = (CUE_OVERLAP if p["cue_overlap"] else 0) | (CUE_UNIQUE if p["cue_unique"] else 0)
         self.s = s
         self._bind()
         P = lib().orc_plane_capacity(ctypes.byref(s))
@@ -302,6 +306,9 @@ class Oracle:
     def fb_unassign(self):
         lib().orc_fb_unassign(self.ref)
 
+    def unique(self):
+        lib().orc_unique(self.ref)
+
     def nnf_update(self, d, level):
         lib().orc_nnf_update(self.ref, d, level)
 
@@ -347,6 +354,8 @@ class Oracle:
                 yield ("symmetry", (lv, stage))
                 yield ("assign", (lv, stage, 0))
             yield ("fb_unassign", ())
+            if p["cue_unique"]:
+                yield ("unique", ())
             yield ("nnf_update", (lv,))
             yield ("eval_cost", (1,))
             for it in range(p["iters"]):
@@ -354,7 +363,7 @@ class Oracle:
                     yield ("pm_halfsweep", (colour, it, lv + 1, 1))
 
     def run_step(self, name, args):
-        if name in ("symmetry", "fb_unassign"):
+        if name in ("symmetry", "fb_unassign", "unique"):
             getattr(self, name)(*args)
             return
         for d in range(2):

@@ -843,8 +843,13 @@ int orc_fb_test(const orc_pair* S, int dir, int px, int py, const double* Hm, co
   return d2 < t;
 }
 
-static int sym_decide(const orc_pair* S, int rk, int pass, int mmin) {
-  return rk >= mmin && (int64_t)pass * S->eta_den > (int64_t)S->eta_num * rk;
+/* Plane symmetry (Alg. 1): |r_k| >= m_min and pass / |r_k| > eta.  With cue 3
+   (Sec. 3.4, third criterion; reading: the share of r_k that the plane's own
+   RANSAC test accepts must also exceed eta), rin / |r_k| > eta as well. */
+static int sym_decide(const orc_pair* S, int rk, int pass, int rin, int mmin) {
+  int ok = rk >= mmin && (int64_t)pass * S->eta_den > (int64_t)S->eta_num * rk;
+  if (S->cues & ORC_CUE_OVERLAP) ok = ok && (int64_t)rin * S->eta_den > (int64_t)S->eta_num * rk;
+  return ok;
 }
 
 void orc_symmetry(orc_pair* S, int level, int stage) {
@@ -858,12 +863,14 @@ void orc_symmetry(orc_pair* S, int level, int stage) {
       int32_t* I = S->pinfo + (size_t)k * ORC_PI_N;
       I[ORC_PI_RK] = 0;
       I[ORC_PI_PASS] = 0;
+      I[ORC_PI_RIN] = 0;
       if (!I[ORC_PI_DETECTED]) {
         I[ORC_PI_VALID] = 0;
         continue;
       }
       const double* Hk = H_of(S, k);
-      int rk = 0, pass = 0, nnear = 0;
+      const double tau2 = S->tau * S->tau;
+      int rk = 0, pass = 0, rin = 0, nnear = 0;
       for (int y = I[ORC_PI_Y0]; y < I[ORC_PI_Y0] + I[ORC_PI_BH]; ++y)
         for (int x = I[ORC_PI_X0]; x < I[ORC_PI_X0] + I[ORC_PI_BW]; ++x) {
           const int p = y * W + x;
@@ -877,24 +884,33 @@ void orc_symmetry(orc_pair* S, int level, int stage) {
             uint8_t ff = 0;
             if (orc_fb_test(S, dir, x, y, Hk, S->twin[1 - dir], &ff)) ++pass;
             if (ff) f = 1;
+            /* the same reprojection test as RANSAC, on the pixel's NNF match */
+            const int32_t v = S->nnf[dir][p];
+            int nr = 0;
+            if (ransac_inlier(Hk, x, y, x + unpack_dx(v), y + unpack_dy(v), tau2, &nr)) ++rin;
+            if (nr) f = 1;
           }
           nnear += f;
         }
       const int mmin = orc_m_min(S, I[ORC_PI_BW], I[ORC_PI_BH]);
       I[ORC_PI_RK] = rk;
       I[ORC_PI_PASS] = pass;
-      I[ORC_PI_VALID] = sym_decide(S, rk, pass, mmin);
+      I[ORC_PI_RIN] = rin;
+      I[ORC_PI_VALID] = sym_decide(S, rk, pass, rin, mmin);
       if (nnear && S->bflag) {
         S->bflag[k] |= 128; /* counts may differ by up to nnear */
         const int d = nnear;
         for (int a = -1; a <= 1; a += 2)
-          for (int c = -1; c <= 1; c += 2) {
-            int rk2 = rk + a * d, ps2 = pass + c * d;
-            if (rk2 < 0) rk2 = 0;
-            if (ps2 < 0) ps2 = 0;
-            if (ps2 > rk2) ps2 = rk2;
-            if (sym_decide(S, rk2, ps2, mmin) != I[ORC_PI_VALID]) S->bflag[k] |= ORC_F_FB;
-          }
+          for (int c = -1; c <= 1; c += 2)
+            for (int e2 = -1; e2 <= 1; e2 += 2) {
+              int rk2 = rk + a * d, ps2 = pass + c * d, ri2 = rin + e2 * d;
+              if (rk2 < 0) rk2 = 0;
+              if (ps2 < 0) ps2 = 0;
+              if (ps2 > rk2) ps2 = rk2;
+              if (ri2 < 0) ri2 = 0;
+              if (ri2 > rk2) ri2 = rk2;
+              if (sym_decide(S, rk2, ps2, ri2, mmin) != I[ORC_PI_VALID]) S->bflag[k] |= ORC_F_FB;
+            }
       }
     }
 }
@@ -928,6 +944,55 @@ void orc_fb_unassign(orc_pair* S) {
 /* O13 + O14: propagate reliable plane matches into the NNF (Sec. 3.3.1,     */
 /* reading R13) and choose each pixel's region distortion (reading R14).    */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Occlusion cue 2 (Sec. 3.4, second criterion: match uniqueness; reading:   */
+/* pixel targets, smallest loss wins, ties to the smallest index, targets    */
+/* rounded as in the NNF update and left out when outside the frame).        */
+/* ------------------------------------------------------------------------ */
+void orc_unique(orc_pair* S) {
+  const int W = S->W, H = S->H, n = W * H;
+  double* best_loss = (double*)malloc(sizeof(double) * (size_t)n);
+  int32_t* best_p = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* target = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int q = 0; q < n; ++q) {
+      best_loss[q] = INFINITY;
+      best_p[q] = -1;
+    }
+    for (int p = 0; p < n; ++p) {
+      target[p] = -1;
+      const int j = S->win[dir][p];
+      if (j < 0) continue;
+      const int x = p % W, y = p / W;
+      double qx, qy;
+      if (!orc_project(H_of(S, j), x, y, &qx, &qy)) continue;
+      if (S->pflag[dir] && (near_half(qx) || near_half(qy))) S->pflag[dir][p] |= ORC_F_ROUND;
+      const double rx = floor(qx + 0.5), ry = floor(qy + 0.5);
+      if (!(rx >= 0 && rx <= W - 1 && ry >= 0 && ry <= H - 1)) continue;
+      const int q = (int)ry * W + (int)rx;
+      target[p] = q;
+      /* pixels in increasing order: a strictly smaller loss takes over, an equal one does not */
+      if (S->loss[dir][p] < best_loss[q] || best_p[q] < 0) {
+        best_loss[q] = S->loss[dir][p];
+        best_p[q] = p;
+      }
+    }
+    for (int p = 0; p < n; ++p) {
+      const int q = target[p];
+      if (q < 0) continue;
+      if (S->pflag[dir] && best_p[q] != p && fabs(S->loss[dir][p] - best_loss[q]) <= TIE_REL * best_loss[q])
+        S->pflag[dir][p] |= ORC_F_COLOUR;
+      if (best_p[q] != p) {
+        S->win[dir][p] = -1;
+        S->loss[dir][p] = INFINITY;
+      }
+    }
+  }
+  free(best_loss);
+  free(best_p);
+  free(target);
+}
+
 void orc_nnf_update(orc_pair* S, int dir, int level) {
   const int W = S->W, H = S->H;
   const int B = S->block[level];
@@ -1027,6 +1092,7 @@ void orc_solve(orc_pair* S, const int32_t* init0, const int32_t* init1, float* f
       for (int dir = 0; dir < 2; ++dir) orc_assign(S, dir, l, stage, 0);
     }
     orc_fb_unassign(S);
+    if (S->cues & ORC_CUE_UNIQUE) orc_unique(S);
     for (int dir = 0; dir < 2; ++dir) {
       orc_nnf_update(S, dir, l);
       orc_eval_cost(S, dir, 1);

@@ -45,7 +45,8 @@ enum {
   ORC_PI_DETECTED,  /* count >= m_min */
   ORC_PI_RK,        /* |r_k|: colour-consistent pixels of the plane in its input set */
   ORC_PI_PASS,      /* pixels of r_k passing the forward-backward test */
-  ORC_PI_VALID,     /* detected and kept by the symmetry test */
+  ORC_PI_VALID,     /* detected and kept by the symmetry test (and, with ORC_CUE_OVERLAP, the overlap test) */
+  ORC_PI_RIN,       /* pixels of r_k that are also RANSAC inliers of the plane (occlusion cue 3) */
   ORC_PI_N
 };
 
@@ -86,7 +87,14 @@ typedef struct orc_pair {
   uint8_t* bflag;               /* per-plane near-tie flags */
   /* statistics */
   int64_t evals;                /* warped-cost evaluations performed */
+  /* optional occlusion cues of Sec. 3.4 beyond the forward-backward symmetry */
+  int32_t cues;                 /* ORC_CUE_* bits */
 } orc_pair;
+
+enum {
+  ORC_CUE_OVERLAP = 1,  /* cue 3: a plane must agree with its colour-consistent region */
+  ORC_CUE_UNIQUE = 2    /* cue 2: of several pixels matched to one target, the higher-loss ones are occluded */
+};
 
 #ifdef __cplusplus
 extern "C" {
@@ -155,6 +163,12 @@ void orc_assign(orc_pair* S, int dir, int level, int stage, int tentative);
    directions, count r_k and FB passes against the other direction's tentative
    winners (twin) and set the valid column. */
 void orc_symmetry(orc_pair* S, int level, int stage);
+/* Occlusion cue 2 (many-to-one matches), both directions: every assigned pixel
+   whose plane sends it (rounded to the grid) to a target inside the frame
+   competes with the other assigned pixels sent to that target; the one with
+   the smallest loss keeps its plane (ties: the smallest pixel index), the
+   others are unassigned. */
+void orc_unique(orc_pair* S);
 /* Forward-backward test FB(p, H) of direction dir against the other direction's
    assignment array `other_win`. */
 int orc_fb_test(const orc_pair* S, int dir, int px, int py, const double* Hm, const int32_t* other_win, uint8_t* flag);

@@ -793,3 +793,98 @@ def test_ransac_ties_keep_lowest_hypothesis():
     o = _ransac_oracle(W, H, 16, fn, hyps=256, seed=5)
     o.ransac(0, 0, 1)
     assert o.pinfo[o.plane_index(0, 0, 1, 0), PI["hyp"]] == first
+
+
+# --------------------------------------------------------------------------
+# Occlusion cues 2 (many-to-one matches) and 3 (plane / colour-region overlap)
+# --------------------------------------------------------------------------
+
+def _project(Hm, x, y):
+    """pi(H p) with the oracle's operation order (w <= 0: no target)."""
+    w = Hm[6] * x + Hm[7] * y + Hm[8]
+    if not w > 0:
+        return 0.0, 0.0, w
+    return (Hm[0] * x + Hm[1] * y + Hm[2]) / w, (Hm[3] * x + Hm[4] * y + Hm[5]) / w, w
+
+
+def test_unique_matches_brute_force():
+    """Cue 2 against its definition evaluated pixel by pixel: among the
+    assigned pixels sent to one in-frame target, only the smallest (loss,
+    index) keeps its plane."""
+    W, H = 40, 30
+    pair = synth.smooth_pair(W, H, seed=31)
+    o = oracle.Oracle(pair.frame1, pair.frame2, C=3, r=2, grad_weight=0.0, blocks=(16,), cue_unique=True)
+    rng = np.random.default_rng(32)
+    planes = [synth.translation(2.25, -1.3), synth.translation(1.0, 0.0), synth.translation(-3.4, 2.2),
+              synth.similarity_about(20, 15, 1.05, 4.0, 0.3, 0.2),
+              np.array([[1.0, 0, 0.2], [0, 1.0, 0.1], [-0.04, 0, 1.0]])]   # w <= 0 right of x = 25
+    ks = [o.plane_index(d, 0, 1, b) for d in range(2) for b in range(len(planes))]
+    for d in range(2):
+        for b, Hm in enumerate(planes):
+            o.pH[o.plane_index(d, 0, 1, b)] = (Hm / Hm[2, 2]).ravel()
+    before = []
+    for d in range(2):
+        pick = rng.integers(-1, len(planes), W * H)
+        o.win[d][:] = np.where(pick >= 0, [o.plane_index(d, 0, 1, max(b, 0)) for b in pick], -1)
+        o.loss[d][:] = np.where(pick >= 0, rng.choice([1e-4, 2e-4, 3e-4], W * H), np.inf)
+        before.append((o.win[d].copy(), o.loss[d].copy()))
+    o.unique()
+    for d in range(2):
+        win0, loss0 = before[d]
+        best = {}
+        targets = {}
+        for p in range(W * H):
+            if win0[p] < 0:
+                continue
+            qx, qy, w = _project(o.pH[win0[p]], p % W, p // W)
+            if not w > 0:
+                continue
+            rx, ry = np.floor(qx + 0.5), np.floor(qy + 0.5)
+            if not (0 <= rx <= W - 1 and 0 <= ry <= H - 1):
+                continue
+            q = int(ry) * W + int(rx)
+            targets[p] = q
+            if q not in best or (loss0[p], p) < (loss0[best[q]], best[q]):
+                best[q] = p
+        exp_win, exp_loss = win0.copy(), loss0.copy()
+        for p, q in targets.items():
+            if best[q] != p:
+                exp_win[p], exp_loss[p] = -1, np.inf
+        assert np.array_equal(o.win[d], exp_win)
+        assert np.array_equal(o.loss[d], exp_loss)
+        assert (exp_win < 0).sum() > (win0 < 0).sum() + 50     # the cue did remove pixels
+
+
+def test_overlap_cue_counts_and_decision():
+    """Cue 3 on an exact translation (the window's plane set to it) whose NNF
+    is right on 40 % of the window, exactly one pixel off on 20 % (not an
+    inlier: the test is strict) and far off elsewhere: the colour-consistent
+    region is the whole in-frame window and only the right 40 % of it are
+    inliers, so the plane is dropped when the cue is on and kept when off."""
+    W, H, B = 64, 48, 16
+    pair = synth.smooth_pair(W, H, seed=33, shift=(3, 2))
+    rng = np.random.default_rng(34)
+    ys, xs = np.mgrid[0:H, 0:W]
+    u = rng.random((H, W))
+    good, one_off = u < 0.4, (u >= 0.4) & (u < 0.6)
+    side = rng.integers(0, 4, (H, W))
+    dx = np.where(good, 3, rng.integers(10, 20, (H, W)))
+    dy = np.where(good, 2, rng.integers(-20, -10, (H, W)))
+    dx = np.where(one_off, 3 + np.array([1, -1, 0, 0])[side], dx)
+    dy = np.where(one_off, 2 + np.array([0, 0, 1, -1])[side], dy)
+    for cue in (False, True):
+        o = oracle.Oracle(pair.frame1, pair.frame2, C=3, r=2, grad_weight=0.0, blocks=(B,), seed=3, cue_overlap=cue)
+        o.set_nnf(0, oracle.pack(dx.ravel(), dy.ravel()))
+        k = o.plane_index(0, 0, 1, 0)
+        o.pH[k] = synth.translation(3, 2).ravel()
+        o.pinfo[k, PI["detected"]] = 1
+        kb = o.plane_index(1, 0, 1, 0)
+        o.pH[kb] = synth.translation(-3, -2).ravel()
+        o.twin[1][:] = kb
+        o.symmetry(0, 1)
+        win = (xs < B) & (ys < B)
+        region = win & (xs + 3 <= W - 1) & (ys + 2 <= H - 1)
+        assert o.pinfo[k, PI["rk"]] == region.sum()
+        assert o.pinfo[k, PI["rin"]] == (region & good).sum()
+        assert o.pinfo[k, PI["pass"]] == region.sum()
+        assert o.pinfo[k, PI["valid"]] == (0 if cue else 1)
