@@ -18,7 +18,8 @@ launches), the dominant kernel's roofline (from an equal number of eager steps
 timed with HIP events around each launch) and the FP64 CPU oracle timed on a
 bounded sample on this host.
 
-Other workloads: --fp16 (FP16 feature storage), --seed, --batched (uneven
+Other workloads: --fp16 (FP16 feature storage), --cues (occlusion cues 2 and
+3 on), --seed, --batched (uneven
 pairs per msgpm_solve_batch), --serving (Poisson arrivals, continuous
 batching).
 """
@@ -61,7 +62,7 @@ def flops_per_eval(kind: str, r: int, C: int) -> int:
     return taps * (12 * C + extra)
 
 
-def cpu_baseline(seconds_hint: float = 25.0) -> dict:
+def cpu_baseline(cues: bool = False) -> dict:
     """The FP64 oracle (single-threaded C) over the whole pipeline on a
     128x56 instance of the same scene generator (lengths scaled by 1/8), same
     method parameters and a first random-search radius of 1024 as in the full
@@ -72,7 +73,7 @@ def cpu_baseline(seconds_hint: float = 25.0) -> dict:
     from paper_1804_03787_amd import synth
     sw, sh = 128, 56
     pair = synth.planar_pair(sw, sh, seed=0, scale=0.125)
-    o = oracle.Oracle(pair.frame1, pair.frame2, R0=1024, **PARAMS)
+    o = oracle.Oracle(pair.frame1, pair.frame2, R0=1024, **dict(PARAMS, cue_overlap=cues, cue_unique=cues))
     t0 = time.perf_counter()
     o.solve()
     dt = time.perf_counter() - t0
@@ -317,6 +318,7 @@ def main() -> int:
                          "plus an eager pass with HIP events around every launch for the per-kernel figures)")
     ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
     ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
+    ap.add_argument("--cues", action="store_true", help="occlusion cues 2 (uniqueness) and 3 (overlap) on")
     ap.add_argument("--batched", action="store_true",
                     help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
     ap.add_argument("--pairs", type=int, default=48)
@@ -342,7 +344,7 @@ def main() -> int:
     pair = synth.planar_pair(W, H, seed=args.seed)
     f1 = torch.from_numpy(pair.frame1).cuda()
     f2 = torch.from_numpy(pair.frame2).cuda()
-    params = dict(PARAMS, fp16=args.fp16)
+    params = dict(PARAMS, fp16=args.fp16, cue_overlap=args.cues, cue_unique=args.cues)
     g = msgpm.Pair(W, H, **params)
     flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
     occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
@@ -414,7 +416,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(args.cues)
 
     line = {
         "metric": "flow Mpix/s (full pipeline)",
@@ -431,7 +433,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
                                "8 PM iterations, 256 RANSAC hypotheses",
-                   "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16)},
+                   "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16),
+                   "occlusion_cues_2_3": bool(args.cues)},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
         "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},

@@ -48,6 +48,17 @@ typedef enum msgpm_status {
 
 /* Storage flag: features stored as binary16 (FP16) with FP32 accumulation. */
 #define MSGPM_FLAG_FP16 1u
+/* Optional occlusion cues of Sec. 3.4 beyond the forward-backward plane
+   symmetry (off by default):
+   cue 3, MSGPM_FLAG_CUE_OVERLAP: a plane is kept only if more than eta of its
+     colour-consistent pixels are also inliers of its own RANSAC test
+     (msgpm_plane.rin / rk);
+   cue 2, MSGPM_FLAG_CUE_UNIQUE: at the end of each level, after the
+     forward-backward check, of the assigned pixels whose plane sends them
+     (rounded to the grid) to the same in-frame target only the one with the
+     smallest loss keeps its plane (ties: smallest pixel index). */
+#define MSGPM_FLAG_CUE_OVERLAP 2u
+#define MSGPM_FLAG_CUE_UNIQUE 4u
 
 /* Method parameters.  Defaults in brackets are those of the 1024x436 workload. */
 typedef struct msgpm_params {
@@ -85,8 +96,8 @@ typedef struct msgpm_plane {
   int32_t refit;             /* 1 if the least-squares refit replaced the hypothesis */
   int32_t detected;          /* count >= minimum support */
   int32_t rk, pass;          /* colour-consistent pixels and those passing forward-backward */
-  int32_t valid;             /* detected and kept by the plane-symmetry test */
-  int32_t reserved;
+  int32_t valid;             /* detected and kept by the plane-symmetry test (and cue 3 if enabled) */
+  int32_t rin;               /* colour-consistent pixels that are also RANSAC inliers of H */
 } msgpm_plane;
 
 /* Byte offsets of every array inside the caller-allocated workspace (one per
@@ -185,12 +196,24 @@ msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stag
 msgpm_status msgpm_assign(const msgpm_params* p, void* d_ws, int level, int stage, int tentative, void* stream);
 
 /* Plane-symmetry test (Alg. 1, Sec. 3.4 first cue) of every detected plane of
-   (level, stage) against the other direction's tentative assignment. */
+   (level, stage) against the other direction's tentative assignment.  Also
+   counts rin (colour-consistent pixels whose NNF match is a RANSAC inlier of the
+   plane); with MSGPM_FLAG_CUE_OVERLAP a valid plane further needs
+   rin / rk > eta (third cue). */
 msgpm_status msgpm_symmetry(const msgpm_params* p, void* d_ws, int level, int stage, void* stream);
 
 /* End-of-level forward-backward check (Sec. 4): assigned pixels failing it
    become unassigned, both directions judged on the same snapshot. */
 msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream);
+
+/* Occlusion cue 2, many-to-one matches (Sec. 3.4, second cue): of the assigned
+   pixels whose plane maps them to the same in-frame pixel (the mapped position
+   rounded half up), only the one with the smallest colour loss keeps its plane,
+   ties to the smallest pixel index; the others become unassigned.  Both
+   directions.  Overwrites the tentative assignment (twin/tloss) as scratch.
+   Runs whatever the flags say; msgpm_solve calls it after msgpm_fb_unassign
+   when MSGPM_FLAG_CUE_UNIQUE is set. */
+msgpm_status msgpm_unique(const msgpm_params* p, void* d_ws, void* stream);
 
 /* NNF update from the assigned planes (Sec. 3.3.1) and region plane choice for
    the next restricted pass. */

@@ -590,6 +590,7 @@ void orc_ransac(orc_pair* S, int dir, int level, int stage) {
       I[ORC_PI_VALID] = 0;
       I[ORC_PI_RK] = 0;
       I[ORC_PI_PASS] = 0;
+      I[ORC_PI_RIN] = 0;
       for (int j = 0; j < 9; ++j) Hk[j] = 0;
       if (n < mmin || n < 4) continue;
       int best = -1, bestc = -1;

@@ -20,6 +20,7 @@ struct DevParams {
   int W, H, C, r;
   int iters, hyps, R0, nk;   // nk: number of random-search radii
   int m_min_abs, eta_num, eta_den, fp16;
+  int cues;                          // MSGPM_FLAG_CUE_* bits
   int n_levels;
   int block[MSGPM_MAX_LEVELS];
   int nbx[MSGPM_MAX_LEVELS], nby[MSGPM_MAX_LEVELS];
@@ -179,6 +180,7 @@ hipError_t launch_assign(const DevParams& P, const Ws& w, int level, int stage, 
 hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
 hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s);
+hipError_t launch_unique(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
                            uint8_t* occ1, hipStream_t s);
 
@@ -201,6 +203,7 @@ enum BatchKind {
   BK_COMMIT,
   BK_NNF_UPDATE,    // a = {level}
   BK_FINALIZE,
+  BK_UNIQUE,        // a = {phase 0..3}: occlusion cue 2
   BK_KINDS
 };
 // Workgroups (x) one pair needs for kernel `kind` with arguments a; grid.y.

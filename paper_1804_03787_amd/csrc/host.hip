@@ -101,7 +101,8 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   if (!(p->inlier_px > 0) || !(p->eps_color > 0) || !(p->fb_px > 0) || !(p->min_support_frac >= 0) ||
       !(p->grad_weight >= 0))
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
-  if (p->flags & ~MSGPM_FLAG_FP16) return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE))
+    return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
   {
     // kernels address one frame's features with 32-bit byte offsets
     const uint64_t px_bytes = (p->flags & MSGPM_FLAG_FP16) ? (p->channels == 3 ? 8 : 12) : 4 * (uint64_t)p->channels;
@@ -124,6 +125,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   d.eta_num = p->eta_num;
   d.eta_den = p->eta_den;
   d.fp16 = (p->flags & MSGPM_FLAG_FP16) ? 1 : 0;
+  d.cues = (int)(p->flags & (MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE));
   d.n_levels = p->n_levels;
   int off = 0;
   for (int l = 0; l < p->n_levels; ++l) {
@@ -329,6 +331,13 @@ msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream) 
   return check(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
 }
 
+msgpm_status msgpm_unique(const msgpm_params* p, void* d_ws, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  return check(timed(MSGPM_T_FB, c.s, [&] { return launch_unique(c.P, c.w, c.s); }), "unique");
+}
+
 msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void* stream) {
   Ctx c;
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
@@ -373,6 +382,7 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
       RUN(timed(MSGPM_T_ASSIGN, c.s, [&] { return launch_assign(c.P, c.w, l, stage, 0, c.s); }), "assign");
     }
     RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
+    if (c.P.cues & MSGPM_FLAG_CUE_UNIQUE) RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_unique(c.P, c.w, c.s); }), "unique");
     RUN(timed(MSGPM_T_NNF_UPDATE, c.s, [&] { return launch_nnf_update(c.P, c.w, l, c.s); }), "nnf_update");
     RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 1, c.s); }), "eval_cost");
     if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
@@ -488,6 +498,8 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
     }
     add(BK_FB, MSGPM_T_FB);
     add(BK_COMMIT, MSGPM_T_FB);
+    if (P.cues & MSGPM_FLAG_CUE_UNIQUE)
+      for (int phase = 0; phase < 4; ++phase) add(BK_UNIQUE, MSGPM_T_FB, phase);
     add(BK_NNF_UPDATE, MSGPM_T_NNF_UPDATE, l);
     add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
     for (int it = 0; it < P.iters; ++it)
@@ -515,9 +527,11 @@ msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevPar
     if (st != MSGPM_OK) return fail(st, "pair %d: %s", i, g_err.c_str());
     const DevParams& a = P[0];
     const DevParams& b = P[i];
-    if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels)
+    if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels ||
+        b.cues != a.cues)
       return fail(MSGPM_E_INVALID,
-                  "pair %d: a batch needs one patch radius, channel count, storage, iteration count and level count",
+                  "pair %d: a batch needs one patch radius, channel count, storage, iteration count, level count "
+                  "and set of occlusion cues",
                   i);
   }
   return MSGPM_OK;

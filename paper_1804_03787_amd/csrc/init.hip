@@ -142,7 +142,7 @@ __device__ __forceinline__ void init_planes_body(const DevParams& P, const Ws& w
   pl.support = pl.count = 0;
   pl.hyp = -1;
   pl.hyp_count = 0;
-  pl.refit = pl.detected = pl.rk = pl.pass = pl.valid = pl.reserved = 0;
+  pl.refit = pl.detected = pl.rk = pl.pass = pl.valid = pl.rin = 0;
   w.planes[k] = pl;
 }
 

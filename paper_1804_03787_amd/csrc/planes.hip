@@ -569,7 +569,7 @@ __device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk
   out.count = 0;
   out.hyp = -1;
   out.hyp_count = 0;
-  out.refit = out.detected = out.rk = out.pass = out.valid = out.reserved = 0;
+  out.refit = out.detected = out.rk = out.pass = out.valid = out.rin = 0;
   if (n < mmin || n < 4) {
     if (t == 0) *pl = out;
     return;
@@ -882,18 +882,20 @@ __global__ __launch_bounds__(kBlock) void kb_assign(const PairDesc* __restrict__
 // Plane symmetry: one workgroup per (window, direction).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void symmetry_body(const DevParams& P, const Ws& w, Blk bk, int level, int stage) {
-  __shared__ int s_rk, s_pass;
+  __shared__ int s_rk, s_pass, s_rin;
   const int t = threadIdx.x, b = bk.x, dir = bk.y;
   msgpm_plane* pl = &w.planes[plane_index(P, dir, level, stage, b)];
   if (t == 0) {
     s_rk = 0;
     s_pass = 0;
+    s_rin = 0;
   }
   __syncthreads();
   if (!pl->detected) {
     if (t == 0) {
       pl->rk = 0;
       pl->pass = 0;
+      pl->rin = 0;
       pl->valid = 0;
     }
     return;
@@ -903,7 +905,7 @@ __device__ __forceinline__ void symmetry_body(const DevParams& P, const Ws& w, B
   double H[9];
   for (int i = 0; i < 9; ++i) H[i] = pl->H[i];
   const int32_t* other = w.twin[1 - dir];
-  int rk = 0, pass = 0;
+  int rk = 0, pass = 0, rin = 0;
   for (int i = t; i < bw * bh; i += kBlock) {
     const int x = x0 + i % bw, y = y0 + i / bw;
     if (stage == 2 && w.win[dir][y * W + x] >= 0) continue;
@@ -911,17 +913,24 @@ __device__ __forceinline__ void symmetry_body(const DevParams& P, const Ws& w, B
     if (e < P.eps2) {
       ++rk;
       pass += fb_test(P, w, x, y, H, other) ? 1 : 0;
+      // cue 3: the plane's own RANSAC test on the pixel's NNF match
+      const int32_t v = w.nnf[dir][y * W + x];
+      rin += ransac_inlier(H, (double)x, (double)y, (double)(x + off_dx(v)), (double)(y + off_dy(v)), P.tau2) ? 1 : 0;
     }
   }
   atomicAdd(&s_rk, rk);
   atomicAdd(&s_pass, pass);
+  atomicAdd(&s_rin, rin);
   __syncthreads();
   if (t == 0) {
     const int mmin_frac = (int)ceil(P.mu * (double)bw * (double)bh);
     const int mmin = mmin_frac > P.m_min_abs ? mmin_frac : P.m_min_abs;
     pl->rk = s_rk;
     pl->pass = s_pass;
-    pl->valid = (s_rk >= mmin && (long long)s_pass * P.eta_den > (long long)P.eta_num * s_rk) ? 1 : 0;
+    pl->rin = s_rin;
+    bool ok = s_rk >= mmin && (long long)s_pass * P.eta_den > (long long)P.eta_num * s_rk;
+    if (P.cues & MSGPM_FLAG_CUE_OVERLAP) ok = ok && (long long)s_rin * P.eta_den > (long long)P.eta_num * s_rk;
+    pl->valid = ok ? 1 : 0;
   }
 }
 
@@ -988,6 +997,58 @@ __global__ __launch_bounds__(kBlock) void kb_commit(const PairDesc* __restrict__
 // ---------------------------------------------------------------------------
 // NNF update from assigned planes and region plane choice.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Occlusion cue 2 (many-to-one matches): per in-frame target, the assigned
+// pixel with the smallest loss keeps its plane, ties to the smallest index.
+// Scratch (free between the FB check and the next assignment): tloss holds
+// each target's smallest loss as its IEEE bits (losses are >= 0, so the
+// unsigned order of the bits is the order of the values), twin the smallest
+// index among the pixels with that loss.  Four launches: clear, minimum loss,
+// minimum index, apply.
+// ---------------------------------------------------------------------------
+__device__ inline int unique_target(const DevParams& P, const Ws& w, int dir, int p) {
+  const int j = w.win[dir][p];
+  if (j < 0) return -1;
+  const int W = P.W, Hh = P.H;
+  double qx, qy;
+  if (!project(w.planes[j].H, (double)(p % W), (double)(p / W), qx, qy)) return -1;
+  const double rx = floor(qx + 0.5), ry = floor(qy + 0.5);
+  if (!(rx >= 0 && rx <= W - 1 && ry >= 0 && ry <= Hh - 1)) return -1;
+  return (int)ry * W + (int)rx;
+}
+
+__device__ __forceinline__ void uq_body(const DevParams& P, const Ws& w, Blk bk, int phase) {
+  const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
+  if (p >= P.W * P.H) return;
+  unsigned long long* best_loss = reinterpret_cast<unsigned long long*>(w.tloss[dir]);
+  int* best_p = w.twin[dir];
+  if (phase == 0) {
+    best_loss[p] = ~0ull;
+    best_p[p] = 0x7fffffff;
+    return;
+  }
+  const int q = unique_target(P, w, dir, p);
+  if (q < 0) return;
+  const unsigned long long key = __double_as_longlong(w.loss[dir][p]);
+  if (phase == 1) {
+    atomicMin(&best_loss[q], key);
+  } else if (phase == 2) {
+    if (best_loss[q] == key) atomicMin(&best_p[q], p);
+  } else if (best_p[q] != p) {
+    w.win[dir][p] = -1;
+    w.loss[dir][p] = __builtin_huge_val();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_unique(DevParams P, Ws w, int phase) { uq_body(P, w, blk_here(), phase); }
+
+__global__ __launch_bounds__(kBlock) void kb_unique(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  uq_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+}
+
 __device__ __forceinline__ void nnf_update_body(const DevParams& P, const Ws& w, Blk bk, int level) {
   const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   const int W = P.W, Hh = P.H;
@@ -1114,6 +1175,15 @@ hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_unique(const DevParams& P, const Ws& w, hipStream_t s) {
+  for (int phase = 0; phase < 4; ++phase) {
+    hipLaunchKernelGGL(k_unique, pixel_grid(P), dim3(kBlock), 0, s, P, w, phase);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s) {
   hipLaunchKernelGGL(k_nnf_update, pixel_grid(P), dim3(kBlock), 0, s, P, w, level);
   return hipGetLastError();
@@ -1154,6 +1224,9 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
       break;
     case BK_FINALIZE:
       hipLaunchKernelGGL(kb_finalize, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_UNIQUE:
+      hipLaunchKernelGGL(kb_unique, grid, block, 0, s, pd, it, n);
       break;
     default:
       return hipErrorInvalidValue;

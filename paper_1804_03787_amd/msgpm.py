@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsgpm.so")
 MAX_LEVELS = 8
 FLAG_FP16 = 1
+FLAG_CUE_OVERLAP = 2  # occlusion cue 3: plane kept only if its consistent pixels mostly match its RANSAC test
+FLAG_CUE_UNIQUE = 4   # occlusion cue 2: one assigned pixel per target
 
 STATUS = {0: "OK", 1: "E_INVALID", 3: "E_DEVICE", 4: "E_UNSUPPORTED"}
 
@@ -52,7 +54,7 @@ class Layout(ctypes.Structure):
 
 
 PLANE_INT_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "support", "count", "hyp",
-                    "hyp_count", "refit", "detected", "rk", "pass", "valid", "reserved"]
+                    "hyp_count", "refit", "detected", "rk", "pass", "valid", "rin"]
 PLANE_DTYPE = np.dtype([("H", "<f8", (9,))] + [(f, "<i4") for f in PLANE_INT_FIELDS])
 assert PLANE_DTYPE.itemsize == 144
 
@@ -80,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_assign": [P, vp, i, i, i, vp],
             "msgpm_symmetry": [P, vp, i, i, vp],
             "msgpm_fb_unassign": [P, vp, vp],
+            "msgpm_unique": [P, vp, vp],
             "msgpm_nnf_update": [P, vp, i, vp],
             "msgpm_finalize": [P, vp, vp, vp, vp, vp, vp],
         }
@@ -139,7 +142,7 @@ def timing_read() -> dict:
 def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 32, 16), iters: int = 8,
                 hyps: int = 256, R0: int = 0, tau: float = 1.0, eps: float = 0.1, tau_fb: float = 1.0,
                 mu: float = 0.25, m_min_abs: int = 8, eta=(1, 2), seed: int = 0, fp16: bool = False,
-                grad_weight: float = 1.0) -> Params:
+                grad_weight: float = 1.0, cue_overlap: bool = False, cue_unique: bool = False) -> Params:
     p = Params()
     p.width, p.height, p.channels, p.patch_radius = width, height, C, r
     blocks = list(blocks)
@@ -148,7 +151,8 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
         p.block[k] = b
     p.pm_iters, p.ransac_hyps, p.search_radius0, p.min_support_abs = iters, hyps, R0, m_min_abs
     p.eta_num, p.eta_den = eta
-    p.flags = FLAG_FP16 if fp16 else 0
+    p.flags = ((FLAG_FP16 if fp16 else 0) | (FLAG_CUE_OVERLAP if cue_overlap else 0) |
+               (FLAG_CUE_UNIQUE if cue_unique else 0))
     p.grad_weight, p.inlier_px, p.eps_color, p.fb_px, p.min_support_frac = grad_weight, tau, eps, tau_fb, mu
     p.seed = seed
     return p
@@ -271,6 +275,9 @@ class Pair:
 
     def fb_unassign(self):
         _call("msgpm_fb_unassign", ctypes.byref(self.p), _ptr(self.ws), _stream())
+
+    def unique(self):
+        _call("msgpm_unique", ctypes.byref(self.p), _ptr(self.ws), _stream())
 
     def nnf_update(self, level):
         _call("msgpm_nnf_update", ctypes.byref(self.p), _ptr(self.ws), level, _stream())
