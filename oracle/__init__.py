@@ -25,7 +25,7 @@ B_RCOUNT, B_SYMCOUNT = 64, 128
 
 DEFAULTS = dict(C=5, r=4, grad_weight=1.0, blocks=(64, 32, 16), iters=8, hyps=256, R0=0, tau=1.0, eps=0.1,
                 tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False, cue_overlap=False,
-                cue_unique=False)
+                cue_unique=False, fill_sweeps=0)
 CUE_OVERLAP, CUE_UNIQUE = 1, 2
 
 
@@ -77,6 +77,7 @@ def lib():
             "orc_fb_test": (i, [P, i, i, i, vp, vp, vp]),
             "orc_fb_unassign": (None, [P]),
             "orc_unique": (None, [P]),
+            "orc_fill": (None, [P]),
             "orc_nnf_update": (None, [P, i, i]),
             "orc_finalize": (None, [P, i, vp, vp]),
             "orc_solve": (None, [P, vp, vp, vp, vp, vp, vp]),
@@ -103,7 +104,7 @@ class _Pair(ctypes.Structure):
         ("loss", ctypes.c_void_p * 2), ("hlabel", ctypes.c_void_p * 2), ("twin", ctypes.c_void_p * 2),
         ("tloss", ctypes.c_void_p * 2), ("pflag", ctypes.c_void_p * 2),
         ("P", ctypes.c_int32), ("pH", ctypes.c_void_p), ("pinfo", ctypes.c_void_p), ("bflag", ctypes.c_void_p),
-        ("evals", ctypes.c_int64), ("cues", ctypes.c_int32),
+        ("evals", ctypes.c_int64), ("cues", ctypes.c_int32), ("fill_sweeps", ctypes.c_int32),
     ]
 
 
@@ -210,6 +211,7 @@ class Oracle:
         s.tau, s.eps, s.tau_fb, s.mu = p["tau"], p["eps"], p["tau_fb"], p["mu"]
         s.seed = p["seed"]
         s.cues = (CUE_OVERLAP if p["cue_overlap"] else 0) | (CUE_UNIQUE if p["cue_unique"] else 0)
+        s.fill_sweeps = p["fill_sweeps"]
         self.s = s
         self._bind()
         P = lib().orc_plane_capacity(ctypes.byref(s))
@@ -309,6 +311,9 @@ class Oracle:
     def unique(self):
         lib().orc_unique(self.ref)
 
+    def fill(self):
+        lib().orc_fill(self.ref)
+
     def nnf_update(self, d, level):
         lib().orc_nnf_update(self.ref, d, level)
 
@@ -361,9 +366,11 @@ class Oracle:
             for it in range(p["iters"]):
                 for colour in range(2):
                     yield ("pm_halfsweep", (colour, it, lv + 1, 1))
+        if p["fill_sweeps"] > 0:
+            yield ("fill", ())
 
     def run_step(self, name, args):
-        if name in ("symmetry", "fb_unassign", "unique"):
+        if name in ("symmetry", "fb_unassign", "unique", "fill"):
             getattr(self, name)(*args)
             return
         for d in range(2):

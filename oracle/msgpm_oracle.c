@@ -994,6 +994,49 @@ void orc_unique(orc_pair* S) {
   free(target);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Filling by homography-model propagation (Sec. 3.4.1, reading R34).        */
+/* ------------------------------------------------------------------------ */
+void orc_fill(orc_pair* S) {
+  const int W = S->W, H = S->H;
+  const double eps2 = S->eps * S->eps;
+  const int nx[4] = {-1, 1, 0, 0}, ny[4] = {0, 0, -1, 1};
+  for (int dir = 0; dir < 2; ++dir) {
+    int32_t* win = S->win[dir];
+    int quiet = 0;
+    for (int t = 0; t < S->fill_sweeps && quiet < 2; ++t) {
+      int filled = 0;
+      for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+          const int p = y * W + x;
+          if ((x + y) % 2 != t % 2 || win[p] != -1) continue;
+          int best = -1;
+          double be = INFINITY;
+          for (int k = 0; k < 4; ++k) {
+            const int qx = x + nx[k], qy = y + ny[k];
+            if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+            const int j = win[qy * W + qx];
+            if (j == -1) continue;
+            const int plane = j >= 0 ? j : -2 - j;
+            const double e = orc_colour_err(S, dir, x, y, H_of(S, plane), NULL);
+            if (e < be || (e == be && plane < best)) {
+              be = e;
+              best = plane;
+            }
+          }
+          if (best >= 0 && be < eps2) {
+            /* this pixel's colour; its neighbours, the only pixels read this
+               half-sweep, have the other colour and are left alone */
+            win[p] = -2 - best;
+            S->loss[dir][p] = be;
+            ++filled;
+          }
+        }
+      quiet = filled ? 0 : quiet + 1;
+    }
+  }
+}
+
 void orc_nnf_update(orc_pair* S, int dir, int level) {
   const int W = S->W, H = S->H;
   const int B = S->block[level];
@@ -1039,11 +1082,12 @@ void orc_finalize(orc_pair* S, int dir, float* flow, uint8_t* occ) {
     for (int x = 0; x < W; ++x) {
       const int p = y * W + x;
       const int j = S->win[dir][p];
+      const int plane = j >= 0 ? j : -2 - j; /* j <= -2: filled */
       double qx, qy;
-      if (j >= 0 && orc_project(H_of(S, j), x, y, &qx, &qy)) {
+      if (j != -1 && orc_project(H_of(S, plane), x, y, &qx, &qy)) {
         flow[2 * p] = (float)(qx - x);
         flow[2 * p + 1] = (float)(qy - y);
-        occ[p] = 0;
+        occ[p] = j >= 0 ? 0 : 2;
       } else {
         flow[2 * p] = (float)unpack_dx(S->nnf[dir][p]);
         flow[2 * p + 1] = (float)unpack_dy(S->nnf[dir][p]);
@@ -1100,6 +1144,7 @@ void orc_solve(orc_pair* S, const int32_t* init0, const int32_t* init1, float* f
     }
     pm_pass(S, l + 1, 1);
   }
+  if (S->fill_sweeps > 0) orc_fill(S);
   orc_finalize(S, 0, flow0, occ0);
   orc_finalize(S, 1, flow1, occ1);
 }

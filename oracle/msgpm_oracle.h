@@ -74,7 +74,7 @@ typedef struct orc_pair {
   /* per-direction pixel state (dir 0: frame 1 -> frame 2, dir 1: frame 2 -> frame 1) */
   int32_t* nnf[2];              /* packed offset: (dx & 0xffff) | (dy << 16) */
   double* cost[2];
-  int32_t* win[2];              /* assigned plane index or -1 */
+  int32_t* win[2];              /* assigned plane index, -1, or -2 - plane if filled */
   double* loss[2];              /* its loss L */
   int32_t* hlabel[2];           /* region plane index for the patch distortion, -1 = identity */
   int32_t* twin[2];             /* tentative / snapshot assignment */
@@ -89,6 +89,9 @@ typedef struct orc_pair {
   int64_t evals;                /* warped-cost evaluations performed */
   /* optional occlusion cues of Sec. 3.4 beyond the forward-backward symmetry */
   int32_t cues;                 /* ORC_CUE_* bits */
+  /* filling by homography-model propagation (Sec. 3.4.1): red-black
+     half-sweeps, 0 = no filling */
+  int32_t fill_sweeps;
 } orc_pair;
 
 enum {
@@ -169,6 +172,15 @@ void orc_symmetry(orc_pair* S, int level, int stage);
    the smallest loss keeps its plane (ties: the smallest pixel index), the
    others are unassigned. */
 void orc_unique(orc_pair* S);
+/* Filling by homography-model propagation (Sec. 3.4.1), both directions, after
+   the last level: fill_sweeps red-black half-sweeps over the unassigned pixels
+   (colour (x + y) % 2 == t % 2 in half-sweep t).  An unassigned pixel takes,
+   of the planes held by its four neighbours (assigned or already filled), the
+   one with the smallest colour error (ties: the smallest plane index) if that
+   error is below eps^2; it is then marked filled: win = -2 - plane,
+   loss = the error.  Stops early after two half-sweeps that fill nothing
+   (nothing can change after them). */
+void orc_fill(orc_pair* S);
 /* Forward-backward test FB(p, H) of direction dir against the other direction's
    assignment array `other_win`. */
 int orc_fb_test(const orc_pair* S, int dir, int px, int py, const double* Hm, const int32_t* other_win, uint8_t* flag);
@@ -176,8 +188,10 @@ int orc_fb_test(const orc_pair* S, int dir, int px, int py, const double* Hm, co
 void orc_fb_unassign(orc_pair* S);
 /* O13 + O14: NNF update from assigned planes and region plane choice. */
 void orc_nnf_update(orc_pair* S, int dir, int level);
-/* O15 outputs: flow (H*W*2, FP32), occlusion mask. Costs of assigned pixels are
-   refreshed under their plane. */
+/* O15 outputs: flow (H*W*2, FP32; a plane's flow where the pixel has one, else
+   its NNF offset), occlusion mask (0 = assigned, 1 = no plane: occluded,
+   2 = filled by model propagation). Costs of assigned pixels are refreshed
+   under their plane. */
 void orc_finalize(orc_pair* S, int dir, float* flow, uint8_t* occ);
 
 /* Whole pipeline (O15) for both directions: init pass, then per level the two

@@ -888,3 +888,124 @@ def test_overlap_cue_counts_and_decision():
         assert o.pinfo[k, PI["rin"]] == (region & good).sum()
         assert o.pinfo[k, PI["pass"]] == region.sum()
         assert o.pinfo[k, PI["valid"]] == (0 if cue else 1)
+
+
+# --------------------------------------------------------------------------
+# Filling by homography-model propagation
+# --------------------------------------------------------------------------
+
+def _rgb_err_at(f1, f2, x, y, tx, ty):
+    """Colour error of pixel (x, y) against the integer target (tx, ty): the
+    mean over R, G, B of the squared difference, summed in channel order."""
+    d = [float(f1[y, x, c]) - float(f2[ty, tx, c]) for c in range(3)]
+    return (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / 3.0
+
+
+@pytest.mark.parametrize("sources", ["random", "one_colour0"])
+def test_fill_reach_matches_red_black_distance(sources):
+    """Every candidate accepted (large epsilon, identity plane): a red-black
+    propagation fills pixel p at half-sweep min over sources s of
+    d(s, p) - 1 + [s has colour 0] (d = 4-neighbour distance), so after K
+    half-sweeps exactly the pixels with that time below K are filled, each
+    with the sources' plane and its own colour error as loss.  A single
+    source of colour 0 leaves the first half-sweep with nothing to fill."""
+    W, H, K = 40, 30, 7
+    pair = synth.smooth_pair(W, H, seed=41)
+    o = oracle.Oracle(pair.frame1, pair.frame2, C=3, r=2, grad_weight=0.0, blocks=(16,), eps=10.0, fill_sweeps=K)
+    rng = np.random.default_rng(42)
+    k = o.plane_index(0, 0, 1, 1)
+    o.pH[k] = np.eye(3).ravel()
+    ys, xs = np.divmod(np.arange(W * H), W)
+    src = rng.random(W * H) < 0.02 if sources == "random" else (xs == 12) & (ys == 14)
+    o.win[0][:] = np.where(src, k, -1)
+    o.win[1][:] = -1
+    o.loss[0][:] = np.where(src, 0.5, np.inf)
+    o.fill()
+    sx, sy = xs[src], ys[src]
+    d = np.abs(xs[:, None] - sx[None, :]) + np.abs(ys[:, None] - sy[None, :])
+    t = (d - 1 + ((sx + sy) % 2 == 0)[None, :]).min(axis=1)
+    filled = ~src & (t < K)
+    assert filled.sum() > (100 if sources == "random" else 40) and (~src & ~filled).sum() > 100
+    assert np.array_equal(o.win[0], np.where(src, k, np.where(filled, -2 - k, -1)))
+    f1, f2 = o.feat[0], o.feat[1]
+    exp = [_rgb_err_at(f1, f2, x, y, x, y) for x, y in zip(xs[filled], ys[filled])]
+    assert np.array_equal(o.loss[0][filled], np.array(exp))
+    assert (o.win[1] == -1).all()
+
+
+def test_fill_stops_at_colour_inconsistent_pixels():
+    """Backward direction of an exact translation, plane sources on one
+    column, a two-column wall of pixels whose colour was changed: the fill
+    covers everything reachable without crossing the wall or the pixels the
+    plane sends out of the frame, and nothing beyond the wall although those
+    pixels are consistent.  The filled pixels' flow is the plane's and their
+    mask value is 2."""
+    W, H = 48, 24
+    pair = synth.smooth_pair(W, H, seed=43, shift=(3, 2))
+    f2 = pair.frame2.copy()
+    f2[:, 20:22] = np.clip(1.0 - f2[:, 20:22], 0, 1) + 0.3
+    o = oracle.Oracle(pair.frame1, f2, C=3, r=2, grad_weight=0.0, blocks=(16,), fill_sweeps=200)
+    k = o.plane_index(1, 0, 2, 0)
+    o.pH[k] = synth.translation(-3, -2).ravel()
+    ys, xs = np.divmod(np.arange(W * H), W)
+    src = xs == 5
+    o.win[1][:] = np.where(src, k, -1)
+    o.loss[1][:] = np.where(src, 0.0, np.inf)
+    o.fill()
+    consistent = np.array([xx >= 3 and yy >= 2 and _rgb_err_at(o.feat[1], o.feat[0], xx, yy, xx - 3, yy - 2) < 0.01
+                           for xx, yy in zip(xs, ys)])
+    assert not consistent[(xs >= 20) & (xs < 22)].any()
+    assert consistent[(xs >= 22) & (ys >= 2)].all()
+    filled = ~src & (xs >= 3) & (xs < 20) & (ys >= 2)
+    assert np.array_equal(o.win[1], np.where(src, k, np.where(filled, -2 - k, -1)))
+    assert (o.loss[1][filled] == 0.0).all()
+    flow, occ = o.finalize(1)
+    fl = flow.reshape(-1, 2)
+    assert (fl[filled] == np.array([-3.0, -2.0], np.float32)).all()
+    assert (occ.ravel()[filled] == 2).all() and (occ.ravel()[src] == 0).all()
+    assert (occ.ravel()[~filled & ~src] == 1).all()
+
+
+def test_fill_takes_smallest_error_then_smallest_index():
+    """A one-pixel gap between a region of plane A (left) and plane B (right):
+    one half-sweep fills the gap pixels of its colour with whichever plane has
+    the smaller colour error there (errors computed here by direct lookup,
+    the planes being integer translations); with B a copy of A stored at a
+    smaller index, the tie goes to B."""
+    W, H, c = 40, 30, 17
+    pair = synth.smooth_pair(W, H, seed=44, shift=(2, 1))
+    ys, xs = np.divmod(np.arange(W * H), W)
+    # gap pixels on rows 1, 5, 9, ... copy plane B's target, so B wins there
+    f1 = pair.frame1.copy()
+    for y in range(1, H - 2, 4):
+        f1[y, c] = pair.frame2[y + 2, c - 1]
+    for tie in (False, True):
+        o = oracle.Oracle(f1, pair.frame2, C=3, r=2, grad_weight=0.0, blocks=(16,), eps=10.0, fill_sweeps=1)
+        ka, kb = o.plane_index(0, 0, 1, 2), o.plane_index(0, 0, 1, 0)
+        ta, tb = (2, 1), ((2, 1) if tie else (-1, 2))
+        o.pH[ka] = synth.translation(*ta).ravel()
+        o.pH[kb] = synth.translation(*tb).ravel()
+        o.win[0][:] = np.where(xs < c, ka, np.where(xs > c, kb, -1))
+        o.loss[0][:] = np.where(xs != c, 0.0, np.inf)
+        o.fill()
+        f1s, f2s = o.feat[0], o.feat[1]
+        n_a = n_b = 0
+        for y in range(H):
+            p = y * W + c
+            if (c + y) % 2 == 1:
+                assert o.win[0][p] == -1
+                continue
+            ea = _rgb_err_at(f1s, f2s, c, y, c + ta[0], y + ta[1]) if 0 <= y + ta[1] < H else np.inf
+            eb = _rgb_err_at(f1s, f2s, c, y, c + tb[0], y + tb[1]) if 0 <= y + tb[1] < H else np.inf
+            if not min(ea, eb) < 100.0:
+                assert o.win[0][p] == -1
+                continue
+            best = kb if (eb < ea or (eb == ea and kb < ka)) else ka
+            n_a += best == ka
+            n_b += best == kb
+            assert o.win[0][p] == -2 - best, (tie, y)
+            assert o.loss[0][p] == min(ea, eb)
+        if tie:
+            assert n_b > 10 and n_a == 0
+        else:
+            assert n_a > 3 and n_b > 3
