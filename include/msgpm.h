@@ -74,6 +74,10 @@ typedef struct msgpm_params {
   int32_t min_support_abs;   /* detection needs max(this, ceil(frac * window area)) inliers [8] */
   int32_t eta_num, eta_den;  /* plane-symmetry ratio eta = num/den [1/2] (Alg. 1, Sec. 3.4) */
   uint32_t flags;            /* MSGPM_FLAG_* */
+  int32_t fill_sweeps;       /* filling by homography-model propagation (Sec. 3.4.1) after the
+                                last level: red-black half-sweeps over the unassigned pixels,
+                                0..65536, 0 = no filling [0]; see msgpm_fill */
+  int32_t reserved;          /* set to 0 */
   double grad_weight;        /* weight of gx, gy in the patch cost [1] */
   double inlier_px;          /* RANSAC reprojection threshold tau in pixels [1] */
   double eps_color;          /* colour-consistency threshold epsilon, RMS over RGB [0.1] (Eq. 4) */
@@ -109,7 +113,8 @@ typedef struct msgpm_layout {
   uint64_t feat_bytes;     /* bytes of one frame's features */
   uint64_t nnf[2];         /* int32 packed offsets */
   uint64_t cost[2];        /* float: warped-patch SSD of the current offset */
-  uint64_t win[2];         /* int32: assigned plane index, -1 = unassigned */
+  uint64_t win[2];         /* int32: assigned plane index, -1 = unassigned,
+                              -2 - k = filled with plane k (after msgpm_fill) */
   uint64_t loss[2];        /* double: colour-consistency loss of the assignment */
   uint64_t hlabel[2];      /* int32: region plane used for the patch distortion, -1 = identity */
   uint64_t twin[2];        /* int32: tentative assignment (scratch) */
@@ -119,7 +124,8 @@ typedef struct msgpm_layout {
   uint64_t active;         /* scratch of restricted half-sweeps: per direction an int32 buffer
                               of ceil(width/2)*height entries (256-byte aligned) listing the
                               pixels to update, those with a region plane from the front,
-                              the others from the back; then 4 uint32 list lengths */
+                              the others from the back; then 4 uint32 list lengths, then
+                              2 x 4 uint32 counters of the filling half-sweeps */
   int32_t n_planes;
   int32_t n_levels;
   int32_t level_blocks[MSGPM_MAX_LEVELS]; /* windows per level and stage */
@@ -140,14 +146,17 @@ const char* msgpm_last_error(void);
  * the end of each level, Sec. 4 set-up): features, initial NNF (random unless
  * given), PatchMatch init pass, then per level two plane stages (Sec. 3.1,
  * 3.2), FB, NNF update (Sec. 3.3.1) and a PatchMatch pass restricted to the
- * unassigned pixels (Sec. 3.3.2).
+ * unassigned pixels (Sec. 3.3.2); then, if fill_sweeps > 0, filling by
+ * model propagation (Sec. 3.4.1).
  *   d_rgb1, d_rgb2: frames, height x width x 3 float32 (HWC).
  *   d_init_nnf0/1:  optional initial NNF per direction (packed, may be NULL).
  *   d_ws:           workspace of layout.total_bytes, 256-byte aligned.
  *   d_flow0/1:      height x width x 2 float32: plane flow where a plane is
- *                   assigned, else the NNF offset.
- *   d_occ0/1:       height x width uint8: 1 = no plane assigned (occluded,
- *                   Sec. 3.4).
+ *                   assigned or filled, else the NNF offset.
+ *   d_occ0/1:       height x width uint8: 0 = plane assigned, 1 = no plane
+ *                   (occluded, Sec. 3.4), 2 = filled by model propagation
+ *                   (no plane of its own: occluded by the same rule, with a
+ *                   neighbour's plane flow).
  * The plane table stays in the workspace (layout.planes).
  * ------------------------------------------------------------------------- */
 msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
@@ -214,6 +223,17 @@ msgpm_status msgpm_fb_unassign(const msgpm_params* p, void* d_ws, void* stream);
    Runs whatever the flags say; msgpm_solve calls it after msgpm_fb_unassign
    when MSGPM_FLAG_CUE_UNIQUE is set. */
 msgpm_status msgpm_unique(const msgpm_params* p, void* d_ws, void* stream);
+
+/* Filling by homography-model propagation (Sec. 3.4.1), both directions:
+   fill_sweeps red-black half-sweeps (half-sweep t updates the pixels with
+   (x + y) % 2 == t % 2).  An unassigned pixel takes, of the planes of its four
+   neighbours (assigned or already filled), the one with the smallest colour
+   error (ties: the smallest plane index) if that error is below eps_color^2;
+   it is then filled: win = -2 - plane, loss = that error.  Half-sweeps after
+   two in a row that filled nothing exit at once (nothing can change).
+   msgpm_solve calls it after the last level when fill_sweeps > 0; filled
+   pixels get their plane's flow and mask value 2. */
+msgpm_status msgpm_fill(const msgpm_params* p, void* d_ws, void* stream);
 
 /* NNF update from the assigned planes (Sec. 3.3.1) and region plane choice for
    the next restricted pass. */
@@ -314,7 +334,8 @@ enum {
   MSGPM_T_FINALIZE = 10,
   MSGPM_T_PM_LIST = 11,            /* pixel lists of the restricted half-sweeps */
   MSGPM_T_PM_RESTRICTED_IDENT = 12, /* restricted half-sweeps, pixels without one (identity patches) */
-  MSGPM_TIMER_KINDS = 13
+  MSGPM_T_FILL = 13,               /* filling by model propagation */
+  MSGPM_TIMER_KINDS = 14
 };
 msgpm_status msgpm_timing_enable(int on);
 msgpm_status msgpm_timing_read(double* ms, int64_t* launches);

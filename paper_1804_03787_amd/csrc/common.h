@@ -21,6 +21,7 @@ struct DevParams {
   int iters, hyps, R0, nk;   // nk: number of random-search radii
   int m_min_abs, eta_num, eta_den, fp16;
   int cues;                          // MSGPM_FLAG_CUE_* bits
+  int fill_sweeps;                   // half-sweeps of the filling, 0 = none
   int n_levels;
   int block[MSGPM_MAX_LEVELS];
   int nbx[MSGPM_MAX_LEVELS], nby[MSGPM_MAX_LEVELS];
@@ -44,7 +45,8 @@ struct Ws {
   msgpm_plane* planes;
   unsigned long long* counters;
   int32_t* act[2];        // pixels a restricted half-sweep updates, per direction
-  unsigned* act_count;    // list lengths [direction][with region plane, without]
+  unsigned* act_count;    // list lengths [direction][with region plane, without], then
+                          // the filling's ring of 4 counts per direction
 };
 
 // Batched launches: one launch covers the same phase of several frame pairs.
@@ -181,6 +183,7 @@ hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage
 hipError_t launch_fb_unassign(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s);
 hipError_t launch_unique(const DevParams& P, const Ws& w, hipStream_t s);
+hipError_t launch_fill(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
                            uint8_t* occ1, hipStream_t s);
 
@@ -204,6 +207,8 @@ enum BatchKind {
   BK_NNF_UPDATE,    // a = {level}
   BK_FINALIZE,
   BK_UNIQUE,        // a = {phase 0..3}: occlusion cue 2
+  BK_FILL_CLEAR,
+  BK_FILL,          // a = {half-sweep}
   BK_KINDS
 };
 // Workgroups (x) one pair needs for kernel `kind` with arguments a; grid.y.

@@ -15,6 +15,10 @@
 
 using namespace msgpm;
 
+// The binding mirrors these structures field by field.
+static_assert(sizeof(msgpm_params) == 136, "msgpm_params layout");
+static_assert(sizeof(msgpm_plane) == 144, "msgpm_plane layout");
+
 namespace {
 
 thread_local std::string g_err;
@@ -103,6 +107,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
   if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE))
     return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->fill_sweeps < 0 || p->fill_sweeps > 65536) return fail(MSGPM_E_INVALID, "fill_sweeps outside 0..65536");
   {
     // kernels address one frame's features with 32-bit byte offsets
     const uint64_t px_bytes = (p->flags & MSGPM_FLAG_FP16) ? (p->channels == 3 ? 8 : 12) : 4 * (uint64_t)p->channels;
@@ -126,6 +131,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   d.eta_den = p->eta_den;
   d.fp16 = (p->flags & MSGPM_FLAG_FP16) ? 1 : 0;
   d.cues = (int)(p->flags & (MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE));
+  d.fill_sweeps = p->fill_sweeps;
   d.n_levels = p->n_levels;
   int off = 0;
   for (int l = 0; l < p->n_levels; ++l) {
@@ -176,7 +182,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     o.counters = cur;
     cur = align256(cur + (uint64_t)kCounterKinds * kCounterStripes * sizeof(uint64_t));
     o.active = cur;
-    cur = align256(cur + 2 * active_list_bytes(d) + 4 * sizeof(uint32_t));
+    cur = align256(cur + 2 * active_list_bytes(d) + 12 * sizeof(uint32_t));
     o.total_bytes = cur;
     o.n_levels = d.n_levels;
     for (int l = 0; l < d.n_levels; ++l) {
@@ -338,6 +344,13 @@ msgpm_status msgpm_unique(const msgpm_params* p, void* d_ws, void* stream) {
   return check(timed(MSGPM_T_FB, c.s, [&] { return launch_unique(c.P, c.w, c.s); }), "unique");
 }
 
+msgpm_status msgpm_fill(const msgpm_params* p, void* d_ws, void* stream) {
+  Ctx c;
+  msgpm_status st = open_ctx(p, d_ws, stream, &c);
+  if (st != MSGPM_OK) return st;
+  return check(timed(MSGPM_T_FILL, c.s, [&] { return launch_fill(c.P, c.w, c.s); }), "fill");
+}
+
 msgpm_status msgpm_nnf_update(const msgpm_params* p, void* d_ws, int level, void* stream) {
   Ctx c;
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
@@ -387,6 +400,7 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
     RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 1, c.s); }), "eval_cost");
     if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
   }
+  if (c.P.fill_sweeps > 0) RUN(timed(MSGPM_T_FILL, c.s, [&] { return launch_fill(c.P, c.w, c.s); }), "fill");
   RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 2, c.s); }), "eval_cost");
   RUN(timed(MSGPM_T_FINALIZE, c.s, [&] { return launch_finalize(c.P, c.w, d_flow0, d_flow1, d_occ0, d_occ1, c.s); }), "finalize");
 #undef RUN
@@ -510,6 +524,10 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
         add(BK_PM_RESTRICTED_IDENT, MSGPM_T_PM_RESTRICTED_IDENT, colour, it, l + 1, 1);
       }
   }
+  if (P.fill_sweeps > 0) {
+    add(BK_FILL_CLEAR, MSGPM_T_FILL);
+    for (int t = 0; t < P.fill_sweeps; ++t) add(BK_FILL, MSGPM_T_FILL, t);
+  }
   add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 2);
   add(BK_FINALIZE, MSGPM_T_FINALIZE);
   return v;
@@ -528,10 +546,10 @@ msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevPar
     const DevParams& a = P[0];
     const DevParams& b = P[i];
     if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels ||
-        b.cues != a.cues)
+        b.cues != a.cues || b.fill_sweeps != a.fill_sweeps)
       return fail(MSGPM_E_INVALID,
-                  "pair %d: a batch needs one patch radius, channel count, storage, iteration count, level count "
-                  "and set of occlusion cues",
+                  "pair %d: a batch needs one patch radius, channel count, storage, iteration count, level count, "
+                  "set of occlusion cues and filling length",
                   i);
   }
   return MSGPM_OK;

@@ -1049,6 +1049,74 @@ __global__ __launch_bounds__(kBlock) void kb_unique(const PairDesc* __restrict__
   uq_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
 }
 
+// ---------------------------------------------------------------------------
+// Filling by homography-model propagation: red-black half-sweeps over the
+// unassigned pixels.  Half-sweep t updates colour t % 2 and reads only the
+// other colour, so pixels update in place.  Each direction keeps a ring of
+// four fill counts: half-sweep t adds into slot t, zeroes slot t + 1 (last
+// written by half-sweep t - 3, read by nobody after t - 1) and exits at once
+// when slots t - 1 and t - 2 are both zero: two half-sweeps in a row that
+// filled nothing leave nothing to fill.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fill_clear_body(const Ws& w) {
+  if (threadIdx.x < 8) w.act_count[4 + threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ void fill_body(const DevParams& P, const Ws& w, Blk bk, int t) {
+  const int dir = bk.y, W = P.W, Hh = P.H;
+  unsigned* ring = w.act_count + 4 + 4 * dir;
+  if (bk.x == 0 && threadIdx.x == 0) ring[(t + 1) & 3] = 0;
+  if (t >= 2 && ring[(t - 1) & 3] == 0 && ring[(t - 2) & 3] == 0) return;  // uniform over the workgroup
+  const int p = bk.x * kBlock + threadIdx.x;
+  int filled = 0;
+  if (p < W * Hh) {
+    const int x = p % W, y = p / W;
+    int32_t* win = w.win[dir];
+    if (((x + y) & 1) == (t & 1) && win[p] == -1) {
+      int best = -1;
+      double be = __builtin_huge_val();
+      const int nx[4] = {x - 1, x + 1, x, x}, ny[4] = {y, y, y - 1, y + 1};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (nx[k] < 0 || nx[k] >= W || ny[k] < 0 || ny[k] >= Hh) continue;
+        const int j = win[ny[k] * W + nx[k]];
+        if (j == -1) continue;
+        const int plane = j >= 0 ? j : -2 - j;
+        const double e = colour_err(P, w, dir, x, y, w.planes[plane].H);
+        if (e < be || (e == be && plane < best)) {
+          be = e;
+          best = plane;
+        }
+      }
+      if (best >= 0 && be < P.eps2) {
+        win[p] = -2 - best;
+        w.loss[dir][p] = be;
+        filled = 1;
+      }
+    }
+  }
+  const int n = __syncthreads_count(filled);
+  if (threadIdx.x == 0 && n) atomicAdd(&ring[t & 3], (unsigned)n);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_clear(Ws w) { fill_clear_body(w); }
+__global__ __launch_bounds__(kBlock) void k_fill(DevParams P, Ws w, int t) { fill_body(P, w, blk_here(), t); }
+
+__global__ __launch_bounds__(kBlock) void kb_fill_clear(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                       int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  fill_clear_body(pd[it[i].pair].w);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_fill(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  fill_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+}
+
 __device__ __forceinline__ void nnf_update_body(const DevParams& P, const Ws& w, Blk bk, int level) {
   const int p = bk.x * kBlock + threadIdx.x, dir = bk.y;
   const int W = P.W, Hh = P.H;
@@ -1103,13 +1171,14 @@ __device__ __forceinline__ void finalize_body(const DevParams& P, const Ws& w, B
   float* flow = dir ? flow1 : flow0;
   uint8_t* occ = dir ? occ1 : occ0;
   const int j = w.win[dir][p];
+  const int plane = j >= 0 ? j : -2 - j;  // j <= -2: filled
   double qx, qy;
-  if (j >= 0 && project(w.planes[j].H, x, y, qx, qy)) {
+  if (j != -1 && project(w.planes[plane].H, x, y, qx, qy)) {
     if (flow) {
       flow[2 * p] = (float)(qx - x);
       flow[2 * p + 1] = (float)(qy - y);
     }
-    if (occ) occ[p] = 0;
+    if (occ) occ[p] = j >= 0 ? 0 : 2;
   } else {
     const int32_t v = w.nnf[dir][p];
     if (flow) {
@@ -1184,6 +1253,16 @@ hipError_t launch_unique(const DevParams& P, const Ws& w, hipStream_t s) {
   return hipSuccess;
 }
 
+hipError_t launch_fill(const DevParams& P, const Ws& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_clear, dim3(1), dim3(kBlock), 0, s, w);
+  hipError_t e = hipGetLastError();
+  for (int t = 0; t < P.fill_sweeps && e == hipSuccess; ++t) {
+    hipLaunchKernelGGL(k_fill, pixel_grid(P), dim3(kBlock), 0, s, P, w, t);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 hipError_t launch_nnf_update(const DevParams& P, const Ws& w, int level, hipStream_t s) {
   hipLaunchKernelGGL(k_nnf_update, pixel_grid(P), dim3(kBlock), 0, s, P, w, level);
   return hipGetLastError();
@@ -1197,7 +1276,7 @@ hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float*
 
 hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, int n, int total, size_t lds,
                                  hipStream_t s) {
-  const dim3 grid(total, 2), block(kBlock);
+  const dim3 grid(total, batch_grid_y(kind)), block(kBlock);
   switch (kind) {
     case BK_RANSAC:
       if (lds > 64 * 1024) {
@@ -1228,6 +1307,12 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
     case BK_UNIQUE:
       hipLaunchKernelGGL(kb_unique, grid, block, 0, s, pd, it, n);
       break;
+    case BK_FILL_CLEAR:
+      hipLaunchKernelGGL(kb_fill_clear, grid, block, 0, s, pd, it, n);
+      break;
+    case BK_FILL:
+      hipLaunchKernelGGL(kb_fill, grid, block, 0, s, pd, it, n);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1236,13 +1321,17 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
 
 int pm_batch_blocks(int kind, const DevParams& P);
 
-int batch_grid_y(int kind) { return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE) ? 1 : 2; }
+int batch_grid_y(int kind) {
+  return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE || kind == BK_FILL_CLEAR) ? 1 : 2;
+}
 
 int batch_blocks(int kind, const DevParams& P, const int* a) {
   const int px = (P.W * P.H + kBlock - 1) / kBlock;
   switch (kind) {
     case BK_FEATURES:
       return (P.W * P.H + 1 + kBlock - 1) / kBlock;
+    case BK_FILL_CLEAR:
+      return 1;
     case BK_INIT_PLANES: {
       const int np = 2 * P.planes_per_dir;
       return ((np > kBlock ? np : kBlock) + kBlock - 1) / kBlock;

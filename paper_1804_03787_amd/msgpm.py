@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
         ("patch_radius", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("block", ctypes.c_int32 * MAX_LEVELS),
         ("pm_iters", ctypes.c_int32), ("ransac_hyps", ctypes.c_int32), ("search_radius0", ctypes.c_int32),
         ("min_support_abs", ctypes.c_int32), ("eta_num", ctypes.c_int32), ("eta_den", ctypes.c_int32),
-        ("flags", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("fill_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("grad_weight", ctypes.c_double), ("inlier_px", ctypes.c_double), ("eps_color", ctypes.c_double),
         ("fb_px", ctypes.c_double), ("min_support_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
@@ -57,6 +57,7 @@ PLANE_INT_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "s
                     "hyp_count", "refit", "detected", "rk", "pass", "valid", "rin"]
 PLANE_DTYPE = np.dtype([("H", "<f8", (9,))] + [(f, "<i4") for f in PLANE_INT_FIELDS])
 assert PLANE_DTYPE.itemsize == 144
+assert ctypes.sizeof(Params) == 136
 
 _lib = None
 
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_symmetry": [P, vp, i, i, vp],
             "msgpm_fb_unassign": [P, vp, vp],
             "msgpm_unique": [P, vp, vp],
+            "msgpm_fill": [P, vp, vp],
             "msgpm_nnf_update": [P, vp, i, vp],
             "msgpm_finalize": [P, vp, vp, vp, vp, vp, vp],
         }
@@ -124,7 +126,7 @@ def _call(name, *args):
 
 
 TIMER_KINDS = ["features", "init", "eval_cost", "pm_init", "pm_restricted", "ransac", "assign", "symmetry", "fb",
-               "nnf_update", "finalize", "pm_list", "pm_restricted_ident"]
+               "nnf_update", "finalize", "pm_list", "pm_restricted_ident", "fill"]
 
 
 def timing_enable(on: bool = True):
@@ -142,7 +144,8 @@ def timing_read() -> dict:
 def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 32, 16), iters: int = 8,
                 hyps: int = 256, R0: int = 0, tau: float = 1.0, eps: float = 0.1, tau_fb: float = 1.0,
                 mu: float = 0.25, m_min_abs: int = 8, eta=(1, 2), seed: int = 0, fp16: bool = False,
-                grad_weight: float = 1.0, cue_overlap: bool = False, cue_unique: bool = False) -> Params:
+                grad_weight: float = 1.0, cue_overlap: bool = False, cue_unique: bool = False,
+                fill_sweeps: int = 0) -> Params:
     p = Params()
     p.width, p.height, p.channels, p.patch_radius = width, height, C, r
     blocks = list(blocks)
@@ -155,6 +158,7 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
                (FLAG_CUE_UNIQUE if cue_unique else 0))
     p.grad_weight, p.inlier_px, p.eps_color, p.fb_px, p.min_support_frac = grad_weight, tau, eps, tau_fb, mu
     p.seed = seed
+    p.fill_sweeps = fill_sweeps
     return p
 
 
@@ -278,6 +282,9 @@ class Pair:
 
     def unique(self):
         _call("msgpm_unique", ctypes.byref(self.p), _ptr(self.ws), _stream())
+
+    def fill(self):
+        _call("msgpm_fill", ctypes.byref(self.p), _ptr(self.ws), _stream())
 
     def nnf_update(self, level):
         _call("msgpm_nnf_update", ctypes.byref(self.p), _ptr(self.ws), level, _stream())

@@ -13,7 +13,8 @@ tests cover single steps of each kind rather than the whole pipeline:
     the three levels (RANSAC stages 1 and 2, assignment, plane symmetry, FB,
     NNF update), one restricted half-sweep after the first level (both the
     distorted-patch kernel over pixels with a region plane and the
-    identity-patch kernel over those without), and the outputs.
+    identity-patch kernel over those without), and the outputs; a third form
+    (scene seed 2) adds occlusion cues 2 and 3 and the filling.
 """
 import numpy as np
 import pytest
@@ -28,8 +29,10 @@ pytestmark = pytest.mark.gpu
 
 W, H = 1024, 436
 FULL = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0, seed=0)
-# (scene seed, FP16 feature storage): the plain FP32 workload and its FP16-storage precision form
-FORMS = {"fp32_seed0": (0, False), "fp16_seed1": (1, True)}
+# (scene seed, FP16 feature storage, further parameters): the plain FP32 workload, its FP16-storage
+# precision form, and the FP32 form with occlusion cues 2 and 3 and 64 half-sweeps of filling
+FORMS = {"fp32_seed0": (0, False, {}), "fp16_seed1": (1, True, {}),
+         "fp32_seed2_cues_fill": (2, False, dict(cue_overlap=True, cue_unique=True, fill_sweeps=64))}
 _pairs = {}
 
 
@@ -63,10 +66,10 @@ def _start(msgpm, pair, p):
     return o, g
 
 
-@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("form", ["fp32_seed0", "fp16_seed1"])
 def test_full_size_initial_pass_step(form):
     msgpm = _need_gpu()
-    seed, fp16 = FORMS[form]
+    seed, fp16, _ = FORMS[form]
     pair = _pair(seed)
     p = dict(FULL, fp16=fp16)
     o, g = _start(msgpm, pair, p)
@@ -105,9 +108,9 @@ def _perturbed_nnf(flow, seed, frac=0.2, amp=16):
 @pytest.mark.parametrize("form", list(FORMS))
 def test_full_size_plane_phases(form):
     msgpm = _need_gpu()
-    seed, fp16 = FORMS[form]
+    seed, fp16, extra = FORMS[form]
     pair = _pair(seed)
-    p = dict(FULL, fp16=fp16)
+    p = dict(FULL, fp16=fp16, **extra)
     o, g = _start(msgpm, pair, p)
     init = [_perturbed_nnf(pair.flow, 1), _perturbed_nnf(synth.ground_truth_backward(pair.layers, W, H), 2)]
     g.init_state(torch.from_numpy(init[0]), torch.from_numpy(init[1]))
@@ -119,9 +122,12 @@ def test_full_size_plane_phases(form):
         for stage in (1, 2):
             steps += [("ransac", (lv, stage)), ("assign", (lv, stage, 1)), ("symmetry", (lv, stage)),
                       ("assign", (lv, stage, 0))]
-        steps += [("fb_unassign", ()), ("nnf_update", (lv,))]
+        steps += [("fb_unassign", ())] + ([("unique", ())] if p.get("cue_unique") else [])
+        steps += [("nnf_update", (lv,))]
         if lv == 0:
             steps += [("eval_cost", (1,)), ("pm_halfsweep", (0, 0, 1, 1))]
+    if p.get("fill_sweeps"):
+        steps += [("fill", ())]
     report = _lockstep(o, g, steps, p)
     assert report["pm_unexplained"] == 0
     # the steps did real work: most pixels end up on a plane, some windows needed stage 2
@@ -138,7 +144,10 @@ def test_full_size_plane_phases(form):
         asg = o.win[d] >= 0
         tol = parity.cost_tol(o.cost[d], FULL["r"], FULL["C"])
         assert (np.abs(c - o.cost[d])[asg] <= tol[asg]).all()
-    print("full-size plane phases", form, report, "assigned", float((o.win[0] >= 0).mean()))
+    if p.get("fill_sweeps"):
+        assert (o.win[0] <= -2).sum() > 1000
+    print("full-size plane phases", form, report, "assigned", float((o.win[0] >= 0).mean()),
+          "filled", float((o.win[0] <= -2).mean()))
 
 
 def test_full_size_fp16_storage_against_fp32_form():

@@ -32,7 +32,7 @@ def _need_gpu():
 
 def _gpu_params(p):
     keys = ("C", "r", "blocks", "iters", "hyps", "R0", "tau", "eps", "tau_fb", "mu", "m_min_abs", "eta", "seed",
-            "fp16", "grad_weight", "cue_overlap", "cue_unique")
+            "fp16", "grad_weight", "cue_overlap", "cue_unique", "fill_sweeps")
     full = dict(oracle.DEFAULTS)
     full.update(p)
     return {k: full[k] for k in keys}
@@ -59,6 +59,9 @@ CASES = {
     # occlusion cues 2 and 3 on: on this pair the uniqueness step unassigns
     # several hundred pixels and the overlap test rejects about twenty planes
     "tiny_cues": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, cue_overlap=True, cue_unique=True)),
+    # filling by model propagation, 64 half-sweeps: on this pair about half of
+    # the unassigned pixels are filled
+    "tiny_fill": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fill_sweeps=64)),
     # the paper's own preset: two levels of 81 and 41 pixel windows (strides 40
     # and 20), 7x7 patches over RGB
     "paper_preset": (lambda: synth.planar_pair(200, 144, seed=11, scale=0.08),
@@ -138,7 +141,7 @@ def _check_step(name, args, o, got, before, p, report):
     elif name == "symmetry":
         bad = parity.compare_planes(o, got["planes"])
         assert not bad, (name, args, bad)
-    elif name in ("fb_unassign", "unique"):
+    elif name in ("fb_unassign", "unique", "fill"):
         for d in range(2):
             assert np.array_equal(got["win"][d], o.win[d]), (name, d)
             assert np.array_equal(got["loss"][d], o.loss[d]), (name, d)
@@ -196,7 +199,7 @@ def test_lockstep_pipeline(case):
     print(case, report)
 
 
-@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues"])
+@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill"])
 def test_solve_end_to_end(case):
     """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
     so the comparison is statistical: offsets, masks and flows of the GPU run

@@ -21,7 +21,8 @@ def _scenes():
         (synth.planar_pair(160, 120, seed=3, scale=0.15), dict(base, seed=5)),
         (synth.planar_pair(97, 61, seed=4, scale=0.1), dict(base, seed=6, blocks=(20, 10))),
         (synth.planar_pair(200, 144, seed=7, scale=0.1), dict(base, seed=7, iters=3)),
-        (synth.tiny_pair(0), dict(base, seed=8, blocks=(24, 12), cue_overlap=True, cue_unique=True)),
+        (synth.tiny_pair(0), dict(base, seed=8, blocks=(24, 12), cue_overlap=True, cue_unique=True,
+                                  fill_sweeps=32)),
         (synth.planar_pair(128, 200, seed=9, scale=0.12), dict(base, seed=9)),
     ]
 
