@@ -25,7 +25,7 @@ B_RCOUNT, B_SYMCOUNT = 64, 128
 
 DEFAULTS = dict(C=5, r=4, grad_weight=1.0, blocks=(64, 32, 16), iters=8, hyps=256, R0=0, tau=1.0, eps=0.1,
                 tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False, cue_overlap=False,
-                cue_unique=False, fill_sweeps=0)
+                cue_unique=False, fill_sweeps=0, histeq=False)
 CUE_OVERLAP, CUE_UNIQUE = 1, 2
 
 
@@ -54,6 +54,7 @@ def lib():
             "orc_philox4x64": (None, [vp, vp, vp]),
             "orc_draw": (ctypes.c_uint32, [ctypes.c_uint64, ctypes.c_uint32]),
             "orc_features": (None, [vp, i, i, i, i, vp]),
+            "orc_histeq": (None, [vp, i, i, vp]),
             "orc_round_fp16": (ctypes.c_float, [ctypes.c_float]),
             "orc_project": (i, [vp, ctypes.c_double, ctypes.c_double, vp, vp]),
             "orc_cost": (ctypes.c_double, [P, i, i, i, i, i, vp]),
@@ -132,6 +133,15 @@ def features(rgb: np.ndarray, C: int = 5, fp16: bool = False) -> np.ndarray:
     return out
 
 
+def histeq(rgb: np.ndarray) -> np.ndarray:
+    """HSV value-channel histogram equalisation of one HWC RGB frame."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.float32)
+    H, W, _ = rgb.shape
+    out = np.empty_like(rgb)
+    lib().orc_histeq(_ptr(rgb), W, H, _ptr(out))
+    return out
+
+
 def round_fp16(x: float) -> float:
     return float(lib().orc_round_fp16(x))
 
@@ -187,6 +197,8 @@ class Oracle:
         self.Hh, self.Ww = frame1.shape[:2]
         H, W = self.Hh, self.Ww
         C = p["C"]
+        if p["histeq"]:
+            frame1, frame2 = histeq(frame1), histeq(frame2)
         self.feat = [features(frame1, C, p["fp16"]), features(frame2, C, p["fp16"])]
         n = W * H
         self.nnf = [np.zeros(n, np.int32) for _ in range(2)]

@@ -123,6 +123,56 @@ void orc_features(const float* rgb, int W, int H, int C, int fp16, float* feat) 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Histogram equalisation of the value channel in HSV (Sec. 4.2; reading     */
+/* R35).  V = max(R, G, B) is binned to 256 levels; level q is mapped to      */
+/* (cdf(q) - cdf_min) / (n - cdf_min), cdf_min being the count of the lowest  */
+/* occupied level.  Changing V alone in HSV scales R, G, B by V' / V; a pixel */
+/* with V <= 0 has no hue or saturation and becomes grey V'.  A frame whose   */
+/* pixels all share one level is left as it is.                              */
+/* ------------------------------------------------------------------------ */
+static int v_level(float V) {
+  const float t = V * 255.0f + 0.5f;
+  if (!(t >= 0.0f)) return 0;
+  if (t >= 255.0f) return 255;
+  return (int)t; /* t >= 0: truncation is the floor */
+}
+
+void orc_histeq(const float* rgb, int W, int H, float* out) {
+  const int64_t n = (int64_t)W * H;
+  int64_t hist[256] = {0};
+  for (int64_t p = 0; p < n; ++p) {
+    const float V = fmaxf(fmaxf(rgb[3 * p], rgb[3 * p + 1]), rgb[3 * p + 2]);
+    ++hist[v_level(V)];
+  }
+  int64_t cdf[256], run = 0, cdf_min = 0;
+  for (int q = 0; q < 256; ++q) {
+    run += hist[q];
+    cdf[q] = run;
+    if (cdf_min == 0) cdf_min = run;
+  }
+  if (cdf_min == n) {
+    memcpy(out, rgb, sizeof(float) * 3 * (size_t)n);
+    return;
+  }
+  float lut[256];
+  for (int q = 0; q < 256; ++q)
+    lut[q] = cdf[q] < cdf_min ? 0.0f : (float)((double)(cdf[q] - cdf_min) / (double)(n - cdf_min));
+  for (int64_t p = 0; p < n; ++p) {
+    const float R = rgb[3 * p], G = rgb[3 * p + 1], B = rgb[3 * p + 2];
+    const float V = fmaxf(fmaxf(R, G), B);
+    const float Vn = lut[v_level(V)];
+    if (V > 0.0f) {
+      const float s = Vn / V;
+      out[3 * p] = R * s;
+      out[3 * p + 1] = G * s;
+      out[3 * p + 2] = B * s;
+    } else {
+      out[3 * p] = out[3 * p + 1] = out[3 * p + 2] = Vn;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Homography (Eq. 1, reading R3: H maps source pixel -> target pixel).      */
 /* ------------------------------------------------------------------------ */
 int orc_project(const double* Hm, double x, double y, double* qx, double* qy) {

@@ -111,6 +111,10 @@ uint32_t orc_draw(uint64_t word, uint32_t n);
 /* Features (O1): rgb is HWC FP32; feat gets C (3 or 5) FP32 channels per pixel.
    fp16 != 0 rounds every feature to binary16 (nearest even) and back. */
 void orc_features(const float* rgb, int W, int H, int C, int fp16, float* feat);
+/* Histogram equalisation of the HSV value channel (Sec. 4.2): rgb and out are
+   HWC FP32 (3 channels), out may not alias rgb.  See the definition above
+   orc_histeq in the source. */
+void orc_histeq(const float* rgb, int W, int H, float* out);
 float orc_round_fp16(float x);
 
 /* Homography projection; returns 0 when the homogeneous w is not positive. */

@@ -1009,3 +1009,81 @@ def test_fill_takes_smallest_error_then_smallest_index():
             assert n_b > 10 and n_a == 0
         else:
             assert n_a > 3 and n_b > 3
+
+
+# --------------------------------------------------------------------------
+# HSV histogram equalisation
+# --------------------------------------------------------------------------
+
+def _grey(values, W, H, seed):
+    rng = np.random.default_rng(seed)
+    v = np.array(values, np.float32)
+    v = v[rng.permutation(v.size)].reshape(H, W)
+    return np.repeat(v[..., None], 3, axis=2)
+
+
+def test_histeq_equal_counts_map_to_even_steps():
+    """A grey frame whose k occupied levels are equally frequent: the i-th
+    level maps to i / (k - 1).  Levels are the nearest of 256 steps, so values
+    0.3/255 and 0.7/255 fall in different levels."""
+    rng = np.random.default_rng(51)
+    k = 17
+    lv = np.sort(rng.choice(256, k, replace=False))
+    vals = np.repeat(lv.astype(np.float32) / np.float32(255), 40)
+    out = oracle.histeq(_grey(vals, 34, 20, 52))
+    src = _grey(vals, 34, 20, 52)
+    idx = np.searchsorted(lv.astype(np.float32) / np.float32(255), src[..., 0])
+    assert np.allclose(out[..., 0], idx / (k - 1), rtol=3e-7, atol=0)
+    assert (out[..., 0] == out[..., 1]).all() and (out[..., 1] == out[..., 2]).all()
+    vals = np.repeat(np.array([0.3, 0.7, 255.0], np.float32) / np.float32(255), 10)
+    out = oracle.histeq(_grey(vals, 6, 5, 53))
+    src = _grey(vals, 6, 5, 53)
+    exp = np.where(src < 0.5 / 255, 0.0, np.where(src < 0.9, 0.5, 1.0))
+    assert np.allclose(out, exp, rtol=3e-7, atol=1e-30)
+
+
+def test_histeq_is_the_empirical_value_distribution():
+    """A colour frame: the new value of a pixel equals the share of pixels
+    whose value level is at or below its own, rescaled so that the lowest
+    occupied level goes to 0 and the highest to 1; the output spans [0, 1]
+    and depends on the value levels only through their order."""
+    rng = np.random.default_rng(54)
+    H, W = 30, 41
+    rgb = (rng.random((H, W, 3)) ** 1.7).astype(np.float32)
+    out = oracle.histeq(rgb)
+    V = rgb.max(axis=2)
+    Vn = out.max(axis=2)
+    lvl = np.floor(V.astype(np.float64) * 255 + 0.5).astype(np.int64).ravel()
+    srt = np.sort(lvl)
+    n = lvl.size
+    at_or_below = np.searchsorted(srt, lvl, side="right")
+    lowest = np.searchsorted(srt, srt[0], side="right")
+    exp = (at_or_below - lowest) / (n - lowest)
+    assert np.allclose(Vn.ravel(), exp, rtol=1e-6, atol=1e-7)
+    assert abs(Vn.min()) < 1e-7 and abs(Vn.max() - 1) < 1e-6
+    # an order-preserving change of the levels leaves the output unchanged
+    grey = np.repeat(np.sort(rng.choice(np.arange(20, 120), 12, replace=False)), 20)
+    a = oracle.histeq(_grey(grey.astype(np.float32) / np.float32(255), 24, 10, 55))
+    b = oracle.histeq(_grey((2 * grey + 7).astype(np.float32) / np.float32(255), 24, 10, 55))
+    assert np.allclose(a, b, rtol=3e-7, atol=0)
+
+
+def test_histeq_keeps_hue_and_saturation():
+    """HSV round trip by an independent library: hue and saturation of every
+    pixel are unchanged; black pixels stay black (the lowest level maps to 0);
+    a frame on a single level is returned as it is."""
+    from matplotlib.colors import rgb_to_hsv
+    rng = np.random.default_rng(56)
+    rgb = rng.random((20, 30, 3)).astype(np.float32)
+    rgb[3, 4] = 0.0
+    rgb[7, 9] = 0.0
+    out = oracle.histeq(rgb)
+    hi, ho = rgb_to_hsv(rgb.astype(np.float64)), rgb_to_hsv(out.astype(np.float64))
+    live = rgb.max(axis=2) > 0
+    assert np.allclose(hi[live][:, 1], ho[live][:, 1], atol=2e-6)
+    dh = np.abs(hi[live][:, 0] - ho[live][:, 0])
+    assert (np.minimum(dh, 1 - dh)[hi[live][:, 1] > 1e-3] < 2e-6).all()
+    assert (out[3, 4] == out[3, 4, 0]).all() and out[3, 4, 0] == 0.0   # lowest level maps to 0
+    flat = np.full((8, 9, 3), 0.25, np.float32)
+    flat[..., 1] = 0.1
+    assert np.array_equal(oracle.histeq(flat), flat)
