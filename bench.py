@@ -19,7 +19,8 @@ timed with HIP events around each launch) and the FP64 CPU oracle timed on a
 bounded sample on this host.
 
 Other workloads: --fp16 (FP16 feature storage), --cues (occlusion cues 2 and
-3 on), --fill N (N half-sweeps of filling by model propagation), --seed,
+3 on), --fill N (N half-sweeps of filling by model propagation), --histeq
+(HSV value equalisation of the frames), --seed,
 --batched (uneven
 pairs per msgpm_solve_batch), --serving (Poisson arrivals, continuous
 batching).
@@ -63,7 +64,7 @@ def flops_per_eval(kind: str, r: int, C: int) -> int:
     return taps * (12 * C + extra)
 
 
-def cpu_baseline(cues: bool = False, fill: int = 0) -> dict:
+def cpu_baseline(cues: bool = False, fill: int = 0, histeq: bool = False) -> dict:
     """The FP64 oracle (single-threaded C) over the whole pipeline on a
     128x56 instance of the same scene generator (lengths scaled by 1/8), same
     method parameters and a first random-search radius of 1024 as in the full
@@ -75,7 +76,7 @@ def cpu_baseline(cues: bool = False, fill: int = 0) -> dict:
     sw, sh = 128, 56
     pair = synth.planar_pair(sw, sh, seed=0, scale=0.125)
     o = oracle.Oracle(pair.frame1, pair.frame2, R0=1024,
-                      **dict(PARAMS, cue_overlap=cues, cue_unique=cues, fill_sweeps=fill))
+                      **dict(PARAMS, cue_overlap=cues, cue_unique=cues, fill_sweeps=fill, histeq=histeq))
     t0 = time.perf_counter()
     o.solve()
     dt = time.perf_counter() - t0
@@ -322,6 +323,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
     ap.add_argument("--cues", action="store_true", help="occlusion cues 2 (uniqueness) and 3 (overlap) on")
     ap.add_argument("--fill", type=int, default=0, help="half-sweeps of filling by model propagation (0 = none)")
+    ap.add_argument("--histeq", action="store_true", help="equalise the frames' HSV value channel first")
     ap.add_argument("--batched", action="store_true",
                     help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
     ap.add_argument("--pairs", type=int, default=48)
@@ -347,7 +349,8 @@ def main() -> int:
     pair = synth.planar_pair(W, H, seed=args.seed)
     f1 = torch.from_numpy(pair.frame1).cuda()
     f2 = torch.from_numpy(pair.frame2).cuda()
-    params = dict(PARAMS, fp16=args.fp16, cue_overlap=args.cues, cue_unique=args.cues, fill_sweeps=args.fill)
+    params = dict(PARAMS, fp16=args.fp16, cue_overlap=args.cues, cue_unique=args.cues, fill_sweeps=args.fill,
+                  histeq=args.histeq)
     g = msgpm.Pair(W, H, **params)
     flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
     occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
@@ -420,7 +423,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.cues, args.fill)
+        cpu = cpu_baseline(args.cues, args.fill, args.histeq)
 
     line = {
         "metric": "flow Mpix/s (full pipeline)",
@@ -438,7 +441,7 @@ def main() -> int:
         "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
                                "8 PM iterations, 256 RANSAC hypotheses",
                    "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16),
-                   "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill},
+                   "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill, "histeq": bool(args.histeq)},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
         "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},

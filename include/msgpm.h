@@ -59,6 +59,14 @@ typedef enum msgpm_status {
      smallest loss keeps its plane (ties: smallest pixel index). */
 #define MSGPM_FLAG_CUE_OVERLAP 2u
 #define MSGPM_FLAG_CUE_UNIQUE 4u
+/* Input flag: histogram-equalise each frame's HSV value channel before the
+   features (the illumination experiment of Sec. 4.2).  V = max(R, G, B) is
+   binned to the nearest of 256 levels, floor(255 V + 1/2) clamped to 0..255;
+   level q maps to V' = (cdf(q) - cdf_min) / (n - cdf_min), where cdf_min is the
+   count of the lowest occupied level (computed in FP64, rounded to FP32).
+   R, G, B are scaled by V'/V (V <= 0: grey V'); a frame whose pixels all share
+   one level is used as it is.  The frames themselves are not modified. */
+#define MSGPM_FLAG_HISTEQ 8u
 
 /* Method parameters.  Defaults in brackets are those of the 1024x436 workload. */
 typedef struct msgpm_params {
@@ -121,6 +129,8 @@ typedef struct msgpm_layout {
   uint64_t tloss[2];       /* double: its loss (scratch) */
   uint64_t planes;         /* msgpm_plane[n_planes] */
   uint64_t counters;       /* uint64[16][64]: evaluation counters, see below */
+  uint64_t histeq;         /* equalisation: uint32 histograms [2][256], FP32 maps [2][256],
+                              int32 single-level flags [2] */
   uint64_t active;         /* scratch of restricted half-sweeps: per direction an int32 buffer
                               of ceil(width/2)*height entries (256-byte aligned) listing the
                               pixels to update, those with a region plane from the front,
@@ -170,7 +180,8 @@ msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float
  * ------------------------------------------------------------------------- */
 
 /* Features of both frames (pixel colours plus optional luma gradients gx, gy
-   with replicate borders; the paper's cost is colour only, Sec. 3.1.3). */
+   with replicate borders; the paper's cost is colour only, Sec. 3.1.3), of
+   the equalised frames with MSGPM_FLAG_HISTEQ. */
 msgpm_status msgpm_features(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2, void* d_ws,
                             void* stream);
 

@@ -22,6 +22,7 @@ struct DevParams {
   int m_min_abs, eta_num, eta_den, fp16;
   int cues;                          // MSGPM_FLAG_CUE_* bits
   int fill_sweeps;                   // half-sweeps of the filling, 0 = none
+  int histeq;                        // equalise the frames' HSV value channel
   int n_levels;
   int block[MSGPM_MAX_LEVELS];
   int nbx[MSGPM_MAX_LEVELS], nby[MSGPM_MAX_LEVELS];
@@ -44,6 +45,7 @@ struct Ws {
   double* tloss[2];
   msgpm_plane* planes;
   unsigned long long* counters;
+  unsigned* heq;          // histograms [2][256], then FP32 maps [2][256], then flags [2]
   int32_t* act[2];        // pixels a restricted half-sweep updates, per direction
   unsigned* act_count;    // list lengths [direction][with region plane, without], then
                           // the filling's ring of 4 counts per direction
@@ -166,7 +168,9 @@ __host__ __device__ inline void cover_range(int n, int B, int nb, int c, int& lo
 }
 
 // ---- launch wrappers (defined in the .hip files) ---------------------------
-hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s);
+hipError_t launch_histeq(const DevParams& P, const Ws& w, const float* rgb1, const float* rgb2, hipStream_t s);
+int heq_hist_blocks(const DevParams& P);
+hipError_t launch_features(const DevParams& P, const Ws& w, const float* rgb, int frame, hipStream_t s);
 hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
                              hipStream_t s);
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s);
@@ -189,6 +193,9 @@ hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float*
 
 // ---- batched launches -------------------------------------------------------
 enum BatchKind {
+  BK_HEQ_CLEAR,     // equalisation: histograms to zero
+  BK_HEQ_HIST,      // grid.y = frame
+  BK_HEQ_MAP,       // grid.y = frame
   BK_FEATURES,      // grid.y = frame
   BK_INIT_PIXELS,
   BK_INIT_PLANES,   // grid.y = 1

@@ -105,7 +105,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   if (!(p->inlier_px > 0) || !(p->eps_color > 0) || !(p->fb_px > 0) || !(p->min_support_frac >= 0) ||
       !(p->grad_weight >= 0))
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
-  if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE))
+  if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE | MSGPM_FLAG_HISTEQ))
     return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->fill_sweeps < 0 || p->fill_sweeps > 65536) return fail(MSGPM_E_INVALID, "fill_sweeps outside 0..65536");
   {
@@ -132,6 +132,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   d.fp16 = (p->flags & MSGPM_FLAG_FP16) ? 1 : 0;
   d.cues = (int)(p->flags & (MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE));
   d.fill_sweeps = p->fill_sweeps;
+  d.histeq = (p->flags & MSGPM_FLAG_HISTEQ) ? 1 : 0;
   d.n_levels = p->n_levels;
   int off = 0;
   for (int l = 0; l < p->n_levels; ++l) {
@@ -181,6 +182,8 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     cur = align256(cur + (uint64_t)o.n_planes * sizeof(msgpm_plane));
     o.counters = cur;
     cur = align256(cur + (uint64_t)kCounterKinds * kCounterStripes * sizeof(uint64_t));
+    o.histeq = cur;
+    cur = align256(cur + (2 * 256 + 2 * 256 + 2) * sizeof(uint32_t));
     o.active = cur;
     cur = align256(cur + 2 * active_list_bytes(d) + 12 * sizeof(uint32_t));
     o.total_bytes = cur;
@@ -209,6 +212,7 @@ Ws make_ws(const DevParams& P, const msgpm_layout& L, void* base) {
   }
   w.planes = reinterpret_cast<msgpm_plane*>(b + L.planes);
   w.counters = reinterpret_cast<unsigned long long*>(b + L.counters);
+  w.heq = reinterpret_cast<unsigned*>(b + L.histeq);
   const uint64_t lb = active_list_bytes(P);
   w.act[0] = reinterpret_cast<int32_t*>(b + L.active);
   w.act[1] = reinterpret_cast<int32_t*>(b + L.active + lb);
@@ -275,9 +279,13 @@ msgpm_status msgpm_features(const msgpm_params* p, const float* d_rgb1, const fl
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if (!d_rgb1 || !d_rgb2) return fail(MSGPM_E_INVALID, "frame pointer is NULL");
-  st = check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s); }), "features");
+  if (c.P.histeq) {
+    st = check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_histeq(c.P, c.w, d_rgb1, d_rgb2, c.s); }), "histeq");
+    if (st != MSGPM_OK) return st;
+  }
+  st = check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb1, 0, c.s); }), "features");
   if (st != MSGPM_OK) return st;
-  return check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s); }), "features");
+  return check(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb2, 1, c.s); }), "features");
 }
 
 msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
@@ -382,8 +390,9 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
     msgpm_status s_ = check((expr), what);       \
     if (s_ != MSGPM_OK) return s_;               \
   } while (0)
-  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb1, const_cast<void*>(c.w.feat[0]), c.s); }), "features");
-  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, d_rgb2, const_cast<void*>(c.w.feat[1]), c.s); }), "features");
+  if (c.P.histeq) RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_histeq(c.P, c.w, d_rgb1, d_rgb2, c.s); }), "histeq");
+  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb1, 0, c.s); }), "features");
+  RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb2, 1, c.s); }), "features");
   RUN(timed(MSGPM_T_INIT, c.s, [&] { return launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s); }), "init_state");
   RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 0, c.s); }), "eval_cost");
   if ((st = run_pm_pass(c, 0, 0)) != MSGPM_OK) return st;
@@ -497,6 +506,11 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
   auto add = [&](int kind, int timer, int a0 = 0, int a1 = 0, int a2 = 0, int a3 = 0) {
     v.push_back(BatchStep{kind, timer, {a0, a1, a2, a3, 0}});
   };
+  if (P.histeq) {
+    add(BK_HEQ_CLEAR, MSGPM_T_FEATURES);
+    add(BK_HEQ_HIST, MSGPM_T_FEATURES);
+    add(BK_HEQ_MAP, MSGPM_T_FEATURES);
+  }
   add(BK_FEATURES, MSGPM_T_FEATURES);
   add(BK_INIT_PIXELS, MSGPM_T_INIT);
   add(BK_INIT_PLANES, MSGPM_T_INIT);
@@ -546,10 +560,10 @@ msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevPar
     const DevParams& a = P[0];
     const DevParams& b = P[i];
     if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels ||
-        b.cues != a.cues || b.fill_sweeps != a.fill_sweeps)
+        b.cues != a.cues || b.fill_sweeps != a.fill_sweeps || b.histeq != a.histeq)
       return fail(MSGPM_E_INVALID,
                   "pair %d: a batch needs one patch radius, channel count, storage, iteration count, level count, "
-                  "set of occlusion cues and filling length",
+                  "set of occlusion cues, filling length and equalisation setting",
                   i);
   }
   return MSGPM_OK;

@@ -15,29 +15,107 @@
 
 namespace msgpm {
 
-__device__ inline float luma(const float* rgb, int p) {
-  const float t = 0.299f * rgb[3 * p];
-  const float u = 0.587f * rgb[3 * p + 1];
-  const float v = 0.114f * rgb[3 * p + 2];
+// ---------------------------------------------------------------------------
+// Equalisation of the HSV value channel (illumination experiment, Sec. 4.2).
+// Histogram: workgroups of kHeqSpan pixels, privatised in LDS, then one global
+// atomic per occupied bin.  Map: one workgroup per frame, inclusive scan of the
+// 256 bins.  The features kernel applies the map to every pixel it reads.
+// ---------------------------------------------------------------------------
+constexpr int kHeqSpan = 16 * kBlock;
+
+__device__ inline int v_level(float V) {
+  const float t = V * 255.0f + 0.5f;
+  if (!(t >= 0.0f)) return 0;
+  if (t >= 255.0f) return 255;
+  return (int)t;
+}
+
+__device__ __forceinline__ void heq_clear_body(const Ws& w) {
+  w.heq[threadIdx.x] = 0;
+  w.heq[kBlock + threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ void heq_hist_body(const float* __restrict__ rgb, int n, unsigned* __restrict__ hist,
+                                              Blk bk) {
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int p0 = bk.x * kHeqSpan;
+  for (int k = 0; k < kHeqSpan / kBlock; ++k) {
+    const int p = p0 + k * kBlock + threadIdx.x;
+    if (p < n) atomicAdd(&h[v_level(fmaxf(fmaxf(rgb[3 * p], rgb[3 * p + 1]), rgb[3 * p + 2]))], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__device__ __forceinline__ void heq_map_body(const unsigned* __restrict__ hist, float* __restrict__ map, int* flag,
+                                             unsigned n) {
+  __shared__ unsigned cdf[256];
+  __shared__ unsigned cmin;
+  const int q = threadIdx.x;
+  const unsigned hq = hist[q];
+  cdf[q] = hq;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive scan (Hillis-Steele)
+    const unsigned v = q >= d ? cdf[q - d] : 0u;
+    __syncthreads();
+    cdf[q] += v;
+    __syncthreads();
+  }
+  if (hq && cdf[q] == hq) cmin = hq;  // the lowest occupied level: nothing below it
+  __syncthreads();
+  const unsigned c = cdf[q], m = cmin;
+  map[q] = c < m ? 0.0f : (float)((double)(c - m) / (double)(n - m));
+  if (q == 0) *flag = m == n ? 1 : 0;
+}
+
+// One pixel of the frame as the method sees it: equalised when map != null.
+__device__ inline void frame_rgb(const float* __restrict__ rgb, int p, const float* __restrict__ map, int flat,
+                                 float out[3]) {
+  const float R = rgb[3 * p], G = rgb[3 * p + 1], B = rgb[3 * p + 2];
+  if (!map || flat) {
+    out[0] = R;
+    out[1] = G;
+    out[2] = B;
+    return;
+  }
+  const float V = fmaxf(fmaxf(R, G), B);
+  const float Vn = map[v_level(V)];
+  if (V > 0.0f) {
+    const float s = Vn / V;
+    out[0] = R * s;
+    out[1] = G * s;
+    out[2] = B * s;
+  } else {
+    out[0] = out[1] = out[2] = Vn;
+  }
+}
+
+__device__ inline float luma(const float* rgb, int p, const float* map, int flat) {
+  float c[3];
+  frame_rgb(rgb, p, map, flat, c);
+  const float t = 0.299f * c[0];
+  const float u = 0.587f * c[1];
+  const float v = 0.114f * c[2];
   return (t + u) + v;
 }
 
 __device__ __forceinline__ void features_body(const float* __restrict__ rgb, int W, int H, int C, int fp16,
-                                              void* __restrict__ feat, Blk bk) {
+                                              const float* __restrict__ map, int flat, void* __restrict__ feat,
+                                              Blk bk) {
   const int p = bk.x * kBlock + threadIdx.x;
   const int n = W * H;
   if (p > n) return;
   float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   if (p < n) {
     const int x = p % W, y = p / W;
-    v[0] = rgb[3 * p];
-    v[1] = rgb[3 * p + 1];
-    v[2] = rgb[3 * p + 2];
+    frame_rgb(rgb, p, map, flat, v);
     if (C == 5) {
       const int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
       const int yu = y > 0 ? y - 1 : 0, yd = y < H - 1 ? y + 1 : H - 1;
-      v[3] = 0.5f * (luma(rgb, y * W + xr) - luma(rgb, y * W + xl));
-      v[4] = 0.5f * (luma(rgb, yd * W + x) - luma(rgb, yu * W + x));
+      v[3] = 0.5f * (luma(rgb, y * W + xr, map, flat) - luma(rgb, y * W + xl, map, flat));
+      v[4] = 0.5f * (luma(rgb, yd * W + x, map, flat) - luma(rgb, yu * W + x, map, flat));
     }
   }
   if (fp16) {
@@ -50,25 +128,83 @@ __device__ __forceinline__ void features_body(const float* __restrict__ rgb, int
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_features(const float* __restrict__ rgb, int W, int H, int C, int fp16,
-                                                    void* __restrict__ feat) {
-  features_body(rgb, W, H, C, fp16, feat, blk_here());
+__device__ inline const float* heq_map(const DevParams& P, const Ws& w, int frame) {
+  return P.histeq ? reinterpret_cast<const float*>(w.heq + 512) + 256 * frame : nullptr;
+}
+__device__ inline int heq_flat(const DevParams& P, const Ws& w, int frame) {
+  return P.histeq ? (int)w.heq[1024 + frame] : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_heq_clear(Ws w) { heq_clear_body(w); }
+
+__global__ __launch_bounds__(kBlock) void k_heq_hist(DevParams P, Ws w, const float* __restrict__ rgb1,
+                                                    const float* __restrict__ rgb2) {
+  const Blk bk = blk_here();
+  heq_hist_body(bk.y ? rgb2 : rgb1, P.W * P.H, w.heq + 256 * bk.y, bk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_heq_map(DevParams P, Ws w) {
+  const int f = blockIdx.y;
+  heq_map_body(w.heq + 256 * f, reinterpret_cast<float*>(w.heq + 512) + 256 * f, reinterpret_cast<int*>(w.heq + 1024 + f),
+               (unsigned)(P.W * P.H));
+}
+
+__global__ __launch_bounds__(kBlock) void k_features(DevParams P, Ws w, const float* __restrict__ rgb, int frame) {
+  features_body(rgb, P.W, P.H, P.C, P.fp16, heq_map(P, w, frame), heq_flat(P, w, frame),
+                const_cast<void*>(w.feat[frame]), blk_here());
 }
 
 // batched: grid.y = frame
+__global__ __launch_bounds__(kBlock) void kb_heq_clear(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                      int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  heq_clear_body(pd[it[i].pair].w);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_heq_hist(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                     int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  heq_hist_body(D.rgb[bk.y], D.P.W * D.P.H, D.w.heq + 256 * bk.y, bk);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_heq_map(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
+                                                    int n) {
+  int i;
+  Blk bk;
+  if (!batch_blk(it, n, i, bk)) return;
+  const PairDesc& D = pd[it[i].pair];
+  const int f = bk.y;
+  heq_map_body(D.w.heq + 256 * f, reinterpret_cast<float*>(D.w.heq + 512) + 256 * f,
+               reinterpret_cast<int*>(D.w.heq + 1024 + f), (unsigned)(D.P.W * D.P.H));
+}
+
 __global__ __launch_bounds__(kBlock) void kb_features(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
                                                      int n) {
   int i;
   Blk bk;
   if (!batch_blk(it, n, i, bk)) return;
   const PairDesc& D = pd[it[i].pair];
-  features_body(D.rgb[bk.y], D.P.W, D.P.H, D.P.C, D.P.fp16, const_cast<void*>(D.w.feat[bk.y]), bk);
+  features_body(D.rgb[bk.y], D.P.W, D.P.H, D.P.C, D.P.fp16, heq_map(D.P, D.w, bk.y), heq_flat(D.P, D.w, bk.y),
+                const_cast<void*>(D.w.feat[bk.y]), bk);
 }
 
-hipError_t launch_features(const DevParams& P, const float* rgb, void* feat, hipStream_t s) {
+int heq_hist_blocks(const DevParams& P) { return (P.W * P.H + kHeqSpan - 1) / kHeqSpan; }
+
+hipError_t launch_histeq(const DevParams& P, const Ws& w, const float* rgb1, const float* rgb2, hipStream_t s) {
+  hipLaunchKernelGGL(k_heq_clear, dim3(1), dim3(kBlock), 0, s, w);
+  hipLaunchKernelGGL(k_heq_hist, dim3(heq_hist_blocks(P), 2), dim3(kBlock), 0, s, P, w, rgb1, rgb2);
+  hipLaunchKernelGGL(k_heq_map, dim3(1, 2), dim3(kBlock), 0, s, P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const DevParams& P, const Ws& w, const float* rgb, int frame, hipStream_t s) {
   const int n = P.W * P.H + 1;  // pixels plus the zero pad pixel
-  hipLaunchKernelGGL(k_features, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, rgb, P.W, P.H, P.C, P.fp16,
-                     feat);
+  hipLaunchKernelGGL(k_features, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P, w, rgb, frame);
   return hipGetLastError();
 }
 
@@ -171,6 +307,15 @@ hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* ini
 
 hipError_t launch_batched_init(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s) {
   switch (kind) {
+    case BK_HEQ_CLEAR:
+      hipLaunchKernelGGL(kb_heq_clear, dim3(total, 1), dim3(kBlock), 0, s, pd, it, n);
+      break;
+    case BK_HEQ_HIST:
+      hipLaunchKernelGGL(kb_heq_hist, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      break;
+    case BK_HEQ_MAP:
+      hipLaunchKernelGGL(kb_heq_map, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      break;
     case BK_FEATURES:
       hipLaunchKernelGGL(kb_features, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
       break;

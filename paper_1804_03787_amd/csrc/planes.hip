@@ -1322,12 +1322,17 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
 int pm_batch_blocks(int kind, const DevParams& P);
 
 int batch_grid_y(int kind) {
-  return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE || kind == BK_FILL_CLEAR) ? 1 : 2;
+  return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE || kind == BK_FILL_CLEAR || kind == BK_HEQ_CLEAR) ? 1 : 2;
 }
 
 int batch_blocks(int kind, const DevParams& P, const int* a) {
   const int px = (P.W * P.H + kBlock - 1) / kBlock;
   switch (kind) {
+    case BK_HEQ_CLEAR:
+    case BK_HEQ_MAP:
+      return 1;
+    case BK_HEQ_HIST:
+      return heq_hist_blocks(P);
     case BK_FEATURES:
       return (P.W * P.H + 1 + kBlock - 1) / kBlock;
     case BK_FILL_CLEAR:
@@ -1355,6 +1360,9 @@ int batch_blocks(int kind, const DevParams& P, const int* a) {
 hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
                           size_t lds, hipStream_t s) {
   switch (kind) {
+    case BK_HEQ_CLEAR:
+    case BK_HEQ_HIST:
+    case BK_HEQ_MAP:
     case BK_FEATURES:
     case BK_INIT_PIXELS:
     case BK_INIT_PLANES:

@@ -19,6 +19,7 @@ MAX_LEVELS = 8
 FLAG_FP16 = 1
 FLAG_CUE_OVERLAP = 2  # occlusion cue 3: plane kept only if its consistent pixels mostly match its RANSAC test
 FLAG_CUE_UNIQUE = 4   # occlusion cue 2: one assigned pixel per target
+FLAG_HISTEQ = 8       # equalise the frames' HSV value channel before the features
 
 STATUS = {0: "OK", 1: "E_INVALID", 3: "E_DEVICE", 4: "E_UNSUPPORTED"}
 
@@ -47,7 +48,7 @@ class Layout(ctypes.Structure):
         ("nnf", ctypes.c_uint64 * 2), ("cost", ctypes.c_uint64 * 2), ("win", ctypes.c_uint64 * 2),
         ("loss", ctypes.c_uint64 * 2), ("hlabel", ctypes.c_uint64 * 2), ("twin", ctypes.c_uint64 * 2),
         ("tloss", ctypes.c_uint64 * 2), ("planes", ctypes.c_uint64), ("counters", ctypes.c_uint64),
-        ("active", ctypes.c_uint64),
+        ("histeq", ctypes.c_uint64), ("active", ctypes.c_uint64),
         ("n_planes", ctypes.c_int32), ("n_levels", ctypes.c_int32),
         ("level_blocks", ctypes.c_int32 * MAX_LEVELS), ("level_nbx", ctypes.c_int32 * MAX_LEVELS),
     ]
@@ -145,7 +146,7 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
                 hyps: int = 256, R0: int = 0, tau: float = 1.0, eps: float = 0.1, tau_fb: float = 1.0,
                 mu: float = 0.25, m_min_abs: int = 8, eta=(1, 2), seed: int = 0, fp16: bool = False,
                 grad_weight: float = 1.0, cue_overlap: bool = False, cue_unique: bool = False,
-                fill_sweeps: int = 0) -> Params:
+                fill_sweeps: int = 0, histeq: bool = False) -> Params:
     p = Params()
     p.width, p.height, p.channels, p.patch_radius = width, height, C, r
     blocks = list(blocks)
@@ -155,7 +156,7 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
     p.pm_iters, p.ransac_hyps, p.search_radius0, p.min_support_abs = iters, hyps, R0, m_min_abs
     p.eta_num, p.eta_den = eta
     p.flags = ((FLAG_FP16 if fp16 else 0) | (FLAG_CUE_OVERLAP if cue_overlap else 0) |
-               (FLAG_CUE_UNIQUE if cue_unique else 0))
+               (FLAG_CUE_UNIQUE if cue_unique else 0) | (FLAG_HISTEQ if histeq else 0))
     p.grad_weight, p.inlier_px, p.eps_color, p.fb_px, p.min_support_frac = grad_weight, tau, eps, tau_fb, mu
     p.seed = seed
     p.fill_sweeps = fill_sweeps

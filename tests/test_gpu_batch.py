@@ -76,17 +76,17 @@ def test_batch_rejects_mixed_shapes():
         msgpm.Batch(gs)
 
 
-def test_batch_with_occlusion_cues_and_filling_matches_single_solves():
+def test_batch_with_cues_filling_and_equalisation_matches_single_solves():
     msgpm = _need_gpu()
     pairs = [synth.tiny_pair(0), synth.planar_pair(97, 61, seed=4, scale=0.1)]
-    base = _gpu_params(dict(TINY_PARAMS, cue_overlap=True, cue_unique=True, fill_sweeps=24))
+    base = _gpu_params(dict(TINY_PARAMS, cue_overlap=True, cue_unique=True, fill_sweeps=24, histeq=True))
     _run(msgpm, pairs, [dict(base), dict(base, seed=6, blocks=(20,))])
 
 
-def test_batch_rejects_mixed_cues_or_filling():
+def test_batch_rejects_mixed_options():
     msgpm = _need_gpu()
     base = _gpu_params(TINY_PARAMS)
-    for other in (dict(base, cue_unique=True), dict(base, fill_sweeps=8)):
+    for other in (dict(base, cue_unique=True), dict(base, fill_sweeps=8), dict(base, histeq=True)):
         gs = [msgpm.Pair(128, 96, **base), msgpm.Pair(128, 96, **other)]
         with pytest.raises(msgpm.MsgpmError):
             msgpm.Batch(gs)

@@ -13,13 +13,14 @@ from tests.test_gpu_parity import _gpu_params, _need_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("size", ["tiny", "tiny_cues_fill", "1024x436"])
+@pytest.mark.parametrize("size", ["tiny", "tiny_options", "1024x436"])
 def test_graph_replays_match_eager(size):
     msgpm = _need_gpu()
     if size == "tiny":
         pr, p = synth.tiny_pair(0), _gpu_params(TINY_PARAMS)
-    elif size == "tiny_cues_fill":
-        pr, p = synth.tiny_pair(0), _gpu_params(dict(TINY_PARAMS, cue_overlap=True, cue_unique=True, fill_sweeps=48))
+    elif size == "tiny_options":
+        pr, p = synth.tiny_pair(0), _gpu_params(dict(TINY_PARAMS, cue_overlap=True, cue_unique=True, fill_sweeps=48,
+                                                      histeq=True))
     else:
         pr = synth.planar_pair(1024, 436, seed=0)
         p = _gpu_params(dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0))

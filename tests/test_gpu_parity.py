@@ -32,7 +32,7 @@ def _need_gpu():
 
 def _gpu_params(p):
     keys = ("C", "r", "blocks", "iters", "hyps", "R0", "tau", "eps", "tau_fb", "mu", "m_min_abs", "eta", "seed",
-            "fp16", "grad_weight", "cue_overlap", "cue_unique", "fill_sweeps")
+            "fp16", "grad_weight", "cue_overlap", "cue_unique", "fill_sweeps", "histeq")
     full = dict(oracle.DEFAULTS)
     full.update(p)
     return {k: full[k] for k in keys}
@@ -62,6 +62,8 @@ CASES = {
     # filling by model propagation, 64 half-sweeps: on this pair about half of
     # the unassigned pixels are filled
     "tiny_fill": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fill_sweeps=64)),
+    # frames equalised in HSV value before the features
+    "tiny_histeq": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, histeq=True)),
     # the paper's own preset: two levels of 81 and 41 pixel windows (strides 40
     # and 20), 7x7 patches over RGB
     "paper_preset": (lambda: synth.planar_pair(200, 144, seed=11, scale=0.08),
@@ -70,15 +72,19 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("histeq", [False, True])
 @pytest.mark.parametrize("fp16", [False, True])
 @pytest.mark.parametrize("C", [3, 5])
-def test_features_bitexact(C, fp16):
+def test_features_bitexact(C, fp16, histeq):
+    """Features of the ragged 77x53 pair, bit for bit; with histeq, of the
+    equalised frames (frame 2 darkened by a gain of 0.6 first)."""
     msgpm = _need_gpu()
     pair = _ragged_pair()
-    g = msgpm.Pair(77, 53, **_gpu_params(dict(C=C, fp16=fp16, blocks=(16,))))
-    g.set_features(pair.frame1, pair.frame2)
-    for f, frame in enumerate((pair.frame1, pair.frame2)):
-        ref = oracle.features(frame, C=C, fp16=fp16)
+    f2 = pair.frame2 * np.float32(0.6) if histeq else pair.frame2
+    g = msgpm.Pair(77, 53, **_gpu_params(dict(C=C, fp16=fp16, blocks=(16,), histeq=histeq)))
+    g.set_features(pair.frame1, f2)
+    for f, frame in enumerate((pair.frame1, f2)):
+        ref = oracle.features(oracle.histeq(frame) if histeq else frame, C=C, fp16=fp16)
         got = g.features(f)
         assert np.array_equal(ref.view(np.uint32), got.view(np.uint32))
 
@@ -199,7 +205,7 @@ def test_lockstep_pipeline(case):
     print(case, report)
 
 
-@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill"])
+@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill", "tiny_histeq"])
 def test_solve_end_to_end(case):
     """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
     so the comparison is statistical: offsets, masks and flows of the GPU run

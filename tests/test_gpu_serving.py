@@ -23,7 +23,7 @@ def _scenes():
         (synth.planar_pair(200, 144, seed=7, scale=0.1), dict(base, seed=7, iters=3)),
         (synth.tiny_pair(0), dict(base, seed=8, blocks=(24, 12), cue_overlap=True, cue_unique=True,
                                   fill_sweeps=32)),
-        (synth.planar_pair(128, 200, seed=9, scale=0.12), dict(base, seed=9)),
+        (synth.planar_pair(128, 200, seed=9, scale=0.12), dict(base, seed=9, histeq=True)),
     ]
 
 
