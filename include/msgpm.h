@@ -131,10 +131,10 @@ typedef struct msgpm_layout {
   uint64_t counters;       /* uint64[16][64]: evaluation counters, see below */
   uint64_t histeq;         /* equalisation: uint32 histograms [2][256], FP32 maps [2][256],
                               int32 single-level flags [2] */
-  uint64_t active;         /* scratch of restricted half-sweeps: per direction an int32 buffer
-                              of ceil(width/2)*height entries (256-byte aligned) listing the
-                              pixels to update, those with a region plane from the front,
-                              the others from the back; then 4 uint32 list lengths, then
+  uint64_t active;         /* scratch of restricted passes: per direction and colour an int32
+                              buffer of ceil(width/2)*height entries (256-byte aligned) listing
+                              the pixels to update, those with a region plane from the front,
+                              the others from the back; then 8 uint32 list lengths, then
                               2 x 4 uint32 counters of the filling half-sweeps */
   int32_t n_planes;
   int32_t n_levels;

@@ -46,8 +46,8 @@ struct Ws {
   msgpm_plane* planes;
   unsigned long long* counters;
   unsigned* heq;          // histograms [2][256], then FP32 maps [2][256], then flags [2]
-  int32_t* act[2];        // pixels a restricted half-sweep updates, per direction
-  unsigned* act_count;    // list lengths [direction][with region plane, without], then
+  int32_t* act[4];        // pixels a restricted half-sweep updates, [direction][colour]
+  unsigned* act_count;    // list lengths [direction][colour][with region plane, without], then
                           // the filling's ring of 4 counts per direction
 };
 
@@ -178,7 +178,7 @@ hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream
 hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
                                hipStream_t s);
 // restricted pass: the pixel lists, then one kernel per list
-hipError_t launch_pm_list(const DevParams& P, const Ws& w, int colour, hipStream_t s);
+hipError_t launch_pm_lists(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
                                 hipStream_t s);
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);

@@ -185,7 +185,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     o.histeq = cur;
     cur = align256(cur + (2 * 256 + 2 * 256 + 2) * sizeof(uint32_t));
     o.active = cur;
-    cur = align256(cur + 2 * active_list_bytes(d) + 12 * sizeof(uint32_t));
+    cur = align256(cur + 4 * active_list_bytes(d) + 16 * sizeof(uint32_t));
     o.total_bytes = cur;
     o.n_levels = d.n_levels;
     for (int l = 0; l < d.n_levels; ++l) {
@@ -214,9 +214,8 @@ Ws make_ws(const DevParams& P, const msgpm_layout& L, void* base) {
   w.counters = reinterpret_cast<unsigned long long*>(b + L.counters);
   w.heq = reinterpret_cast<unsigned*>(b + L.histeq);
   const uint64_t lb = active_list_bytes(P);
-  w.act[0] = reinterpret_cast<int32_t*>(b + L.active);
-  w.act[1] = reinterpret_cast<int32_t*>(b + L.active + lb);
-  w.act_count = reinterpret_cast<unsigned*>(b + L.active + 2 * lb);
+  for (int k = 0; k < 4; ++k) w.act[k] = reinterpret_cast<int32_t*>(b + L.active + k * lb);
+  w.act_count = reinterpret_cast<unsigned*>(b + L.active + 4 * lb);
   return w;
 }
 
@@ -243,17 +242,57 @@ msgpm_status check_level(const Ctx& c, int level, int stage) {
   return MSGPM_OK;
 }
 
+// A second stream of the calling thread (one per device), on which the
+// identity-patch launch of a restricted half-sweep runs beside the
+// distorted-patch launch: the two update disjoint pixels of one colour and
+// only read the other colour.  Created on first use and kept for the life of
+// the thread; default priority.
+struct Aux {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+thread_local std::map<int, Aux> t_aux;
+
+hipError_t aux_stream(Aux** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  Aux& a = t_aux[dev];
+  if (!a.s) {
+    if ((e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *out = &a;
+  return hipSuccess;
+}
+
+msgpm_status run_lists(const Ctx& c) {
+  return check(timed(MSGPM_T_PM_LIST, c.s, [&] { return launch_pm_lists(c.P, c.w, c.s); }), "pm_list");
+}
+
+// One half-sweep; a restricted one reads the lists run_lists built.
 msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted) {
   if (!restricted)
     return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_halfsweep");
-  msgpm_status st = check(timed(MSGPM_T_PM_LIST, c.s, [&] { return launch_pm_list(c.P, c.w, colour, c.s); }), "pm_list");
-  if (st != MSGPM_OK) return st;
-  st = check(timed(MSGPM_T_PM_RESTRICTED, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_restricted");
-  if (st != MSGPM_OK) return st;
-  return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, c.s); }), "pm_restricted");
+  msgpm_status st;
+  Aux* a = nullptr;
+  if ((st = check(aux_stream(&a), "second stream")) != MSGPM_OK) return st;
+  if ((st = check(hipEventRecord(a->fork, c.s), "fork")) != MSGPM_OK) return st;
+  if ((st = check(hipStreamWaitEvent(a->s, a->fork, 0), "fork")) != MSGPM_OK) return st;
+  // fork: identity patches on the second stream, distorted ones on the caller's; always joined
+  msgpm_status st1 = check(timed(MSGPM_T_PM_RESTRICTED_IDENT, a->s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, a->s); }), "pm_restricted");
+  msgpm_status st0 = check(timed(MSGPM_T_PM_RESTRICTED, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_restricted");
+  if ((st = check(hipEventRecord(a->join, a->s), "join")) != MSGPM_OK) return st;
+  if ((st = check(hipStreamWaitEvent(c.s, a->join, 0), "join")) != MSGPM_OK) return st;
+  return st1 != MSGPM_OK ? st1 : st0;
 }
 
 msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
+  if (restricted) {
+    msgpm_status st = run_lists(c);
+    if (st != MSGPM_OK) return st;
+  }
   for (int it = 0; it < c.P.iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       msgpm_status st = run_halfsweep(c, colour, it, slot, restricted);
@@ -311,6 +350,7 @@ msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, i
   if (st != MSGPM_OK) return st;
   if (colour != 0 && colour != 1) return fail(MSGPM_E_INVALID, "colour must be 0 or 1");
   if (iter < 0 || slot < 0 || slot > 255) return fail(MSGPM_E_INVALID, "iter or slot out of range");
+  if (restricted && (st = run_lists(c)) != MSGPM_OK) return st;
   return run_halfsweep(c, colour, iter, slot, restricted ? 1 : 0);
 }
 
@@ -460,6 +500,8 @@ msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const
       return st;
     Ctx cc = c;
     cc.s = g_graphs.capture;
+    Aux* aux = nullptr;  // created outside the capture; joins it through the fork event
+    if ((st = check(aux_stream(&aux), "second stream")) != MSGPM_OK) return st;
     if ((st = check(hipStreamBeginCapture(cc.s, hipStreamCaptureModeThreadLocal), "graph capture")) != MSGPM_OK)
       return st;
     g_capturing = true;
@@ -530,10 +572,10 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
       for (int phase = 0; phase < 4; ++phase) add(BK_UNIQUE, MSGPM_T_FB, phase);
     add(BK_NNF_UPDATE, MSGPM_T_NNF_UPDATE, l);
     add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
+    add(BK_ZERO_ACTIVE, MSGPM_T_PM_LIST);
+    for (int colour = 0; colour < 2; ++colour) add(BK_ACTIVE_LIST, MSGPM_T_PM_LIST, colour);
     for (int it = 0; it < P.iters; ++it)
       for (int colour = 0; colour < 2; ++colour) {
-        add(BK_ZERO_ACTIVE, MSGPM_T_PM_LIST);
-        add(BK_ACTIVE_LIST, MSGPM_T_PM_LIST, colour);
         add(BK_PM_RESTRICTED, MSGPM_T_PM_RESTRICTED, colour, it, l + 1, 1);
         add(BK_PM_RESTRICTED_IDENT, MSGPM_T_PM_RESTRICTED_IDENT, colour, it, l + 1, 1);
       }

@@ -600,12 +600,12 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
 // runs, and the update of a pixel does not depend on it.
 // ---------------------------------------------------------------------------
 __global__ void k_zero_active(Ws w) {
-  if (threadIdx.x < 4) w.act_count[threadIdx.x] = 0u;
+  if (threadIdx.x < 8) w.act_count[threadIdx.x] = 0u;
 }
 
 // batched: one workgroup per item
 __global__ void kb_zero_active(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  if (threadIdx.x < 4 && (int)blockIdx.x < n) pd[it[blockIdx.x].pair].w.act_count[threadIdx.x] = 0u;
+  if (threadIdx.x < 8 && (int)blockIdx.x < n) pd[it[blockIdx.x].pair].w.act_count[threadIdx.x] = 0u;
 }
 
 constexpr int kListSpan = 4;  // pixels of the colour per thread of k_active_list
@@ -647,7 +647,7 @@ __device__ __forceinline__ void active_list_body(const DevParams& P, const Ws& w
   if (t < 2) {
     unsigned total = 0u;
     for (int k = 0; k < NS; ++k) total += s_cnt[t][k];
-    s_base[t] = total ? atomicAdd(&w.act_count[2 * dir + t], total) : 0u;
+    s_base[t] = total ? atomicAdd(&w.act_count[2 * (2 * dir + colour) + t], total) : 0u;
   }
   __syncthreads();
   unsigned posA = s_base[0], posB = s_base[1];
@@ -660,8 +660,9 @@ __device__ __forceinline__ void active_list_body(const DevParams& P, const Ws& w
       posA += s_cnt[0][done];
       posB += s_cnt[1][done];
     }
-    if (inA[k]) w.act[dir][posA + __popcll(mA[k] & lt)] = pix[k];
-    if (inB[k]) w.act[dir][cap - 1u - (posB + __popcll(mB[k] & lt))] = pix[k];
+    int32_t* list = w.act[2 * dir + colour];
+    if (inA[k]) list[posA + __popcll(mA[k] & lt)] = pix[k];
+    if (inB[k]) list[cap - 1u - (posB + __popcll(mB[k] & lt))] = pix[k];
   }
 }
 
@@ -696,14 +697,14 @@ __device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& 
   if (restricted) {
     // only the workgroups covering the list work; each XCD takes a contiguous
     // part.  Distorted patches: the front list; identity patches: the back one.
-    const unsigned cnt = w.act_count[2 * dir + (IDENT ? 1 : 0)];
+    const unsigned cnt = w.act_count[2 * (2 * dir + colour) + (IDENT ? 1 : 0)];
     constexpr unsigned per = NG * (kBlock / kWave);
     const int nb = (int)((cnt + per - 1) / per);
     if (bk.x >= nb) return;
     const long long i = ((long long)xcd_remap(bk.x, nb) * (kBlock / kWave) + wave) * NG + g;
     act = g < NG && i < (long long)cnt;
     const unsigned cap = (unsigned)Wh * (unsigned)H;
-    const int q = act ? w.act[dir][IDENT ? cap - 1u - (unsigned)i : (unsigned)i] : 0;
+    const int q = act ? w.act[2 * dir + colour][IDENT ? cap - 1u - (unsigned)i : (unsigned)i] : 0;
     y = q / W;
     x = q - y * W;
   } else {
@@ -819,14 +820,18 @@ static hipError_t dispatch_restricted(const DevParams& P, const Ws& w, int colou
   return pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, 1, s);
 }
 
-hipError_t launch_pm_list(const DevParams& P, const Ws& w, int colour, hipStream_t s) {
+// The lists of both colours; they hold for every half-sweep of a restricted
+// pass (assignment and region planes do not change during it).
+hipError_t launch_pm_lists(const DevParams& P, const Ws& w, hipStream_t s) {
   const long long n = (long long)((P.W + 1) >> 1) * P.H;
   hipLaunchKernelGGL(k_zero_active, dim3(1), dim3(kWave), 0, s, w);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const long long span = (long long)kListSpan * kBlock;
-  hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
-  return hipGetLastError();
+  for (int colour = 0; colour < 2 && e == hipSuccess; ++colour) {
+    hipLaunchKernelGGL(k_active_list, dim3((unsigned)((n + span - 1) / span), 2), dim3(kBlock), 0, s, P, w, colour);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 template <int R, int C, bool FP16, bool IDENT>

@@ -1059,12 +1059,12 @@ __global__ __launch_bounds__(kBlock) void kb_unique(const PairDesc* __restrict__
 // filled nothing leave nothing to fill.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fill_clear_body(const Ws& w) {
-  if (threadIdx.x < 8) w.act_count[4 + threadIdx.x] = 0;
+  if (threadIdx.x < 8) w.act_count[8 + threadIdx.x] = 0;
 }
 
 __device__ __forceinline__ void fill_body(const DevParams& P, const Ws& w, Blk bk, int t) {
   const int dir = bk.y, W = P.W, Hh = P.H;
-  unsigned* ring = w.act_count + 4 + 4 * dir;
+  unsigned* ring = w.act_count + 8 + 4 * dir;
   if (bk.x == 0 && threadIdx.x == 0) ring[(t + 1) & 3] = 0;
   if (t >= 2 && ring[(t - 1) & 3] == 0 && ring[(t - 2) & 3] == 0) return;  // uniform over the workgroup
   const int p = bk.x * kBlock + threadIdx.x;
