@@ -565,16 +565,17 @@ int orc_refit(const double* sx, const double* sy, const double* dx, const double
   return denormalise(h, s1, c1x, c1y, s2, c2x, c2y, Hout);
 }
 
-/* Reprojection inlier test (reading R7), division-free form; *near set when the
-   decision is within the near-tie band. */
+/* Reprojection inlier test (reading R7), division-free form: w > 0 and
+   |(u, v) - w q|^2 < tau^2 w^2, each product-plus-sum rounded once (fma, reading
+   R31); *near set when the decision is within the near-tie band. */
 static int ransac_inlier(const double* Hm, double x, double y, double qx, double qy, double tau2, int* near) {
-  double w = Hm[6] * x + Hm[7] * y + Hm[8];
+  const double w = fma(Hm[6], x, fma(Hm[7], y, Hm[8]));
   if (!(w > 0)) return 0;
-  double u = Hm[0] * x + Hm[1] * y + Hm[2];
-  double v = Hm[3] * x + Hm[4] * y + Hm[5];
-  double ex = u - w * qx, ey = v - w * qy;
-  double e2 = ex * ex + ey * ey;
-  double t = tau2 * w * w;
+  const double u = fma(Hm[0], x, fma(Hm[1], y, Hm[2]));
+  const double v = fma(Hm[3], x, fma(Hm[4], y, Hm[5]));
+  const double ex = fma(-w, qx, u), ey = fma(-w, qy, v);
+  const double e2 = fma(ex, ex, ey * ey);
+  const double t = tau2 * w * w;
   if (fabs(e2 - t) <= TIE_REL * t) *near = 1;
   return e2 < t;
 }

@@ -243,14 +243,15 @@ __device__ inline bool dlt4(const double (&sx)[4], const double (&sy)[4], const 
   return denormalise(h, s1, c1x, c1y, s2, c2x, c2y, Hout);
 }
 
-// Reprojection inlier test, division-free: w > 0 and |(u, v) - w q|^2 < tau^2 w^2.
+// Reprojection inlier test, division-free: w > 0 and |(u, v) - w q|^2 < tau^2 w^2,
+// each product-plus-sum a fused multiply-add (rounded once).
 __device__ inline bool ransac_inlier(const double* H, double x, double y, double qx, double qy, double tau2) {
-  const double w = H[6] * x + H[7] * y + H[8];
+  const double w = fma(H[6], x, fma(H[7], y, H[8]));
   if (!(w > 0)) return false;
-  const double u = H[0] * x + H[1] * y + H[2];
-  const double v = H[3] * x + H[4] * y + H[5];
-  const double ex = u - w * qx, ey = v - w * qy;
-  const double e2 = ex * ex + ey * ey;
+  const double u = fma(H[0], x, fma(H[1], y, H[2]));
+  const double v = fma(H[3], x, fma(H[4], y, H[5]));
+  const double ex = fma(-w, qx, u), ey = fma(-w, qy, v);
+  const double e2 = fma(ex, ex, ey * ey);
   const double t = tau2 * w * w;
   return e2 < t;
 }
@@ -296,11 +297,11 @@ static_assert(kMdChunk == kBlock - kWave && kNeChunk * 6 == kBlock - kWave, "pro
 // Inlier test against 8 coefficients with h8 = 1 (the DLT and the refit
 // normalise to it), same operations as ransac_inlier.
 __device__ inline bool inlier8(const double* H, double x, double y, double qx, double qy, double tau2) {
-  const double w = H[6] * x + H[7] * y + 1.0;
-  const double u = H[0] * x + H[1] * y + H[2];
-  const double v = H[3] * x + H[4] * y + H[5];
-  const double ex = u - w * qx, ey = v - w * qy;
-  const double e2 = ex * ex + ey * ey;
+  const double w = fma(H[6], x, fma(H[7], y, 1.0));
+  const double u = fma(H[0], x, fma(H[1], y, H[2]));
+  const double v = fma(H[3], x, fma(H[4], y, H[5]));
+  const double ex = fma(-w, qx, u), ey = fma(-w, qy, v);
+  const double e2 = fma(ex, ex, ey * ey);
   const double t = tau2 * w * w;
   return (w > 0) && (e2 < t);
 }
@@ -476,11 +477,11 @@ __device__ inline void score_batch(const double* aux, const unsigned long long* 
       int c = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double w = Hc[6] * X[u] + Hc[7] * Y[u] + 1.0;
-        const double uu = Hc[0] * X[u] + Hc[1] * Y[u] + Hc[2];
-        const double vv = Hc[3] * X[u] + Hc[4] * Y[u] + Hc[5];
-        const double ex = uu - w * QX[u], ey = vv - w * QY[u];
-        const double e2 = ex * ex + ey * ey;
+        const double w = fma(Hc[6], X[u], fma(Hc[7], Y[u], 1.0));
+        const double uu = fma(Hc[0], X[u], fma(Hc[1], Y[u], Hc[2]));
+        const double vv = fma(Hc[3], X[u], fma(Hc[4], Y[u], Hc[5]));
+        const double ex = fma(-w, QX[u], uu), ey = fma(-w, QY[u], vv);
+        const double e2 = fma(ex, ex, ey * ey);
         const double t = tau2 * w * w;
         const unsigned long long pos = __ballot(w > 0), close = __ballot(e2 < t);
         c += __popcll(pos & close & vm[u]);
