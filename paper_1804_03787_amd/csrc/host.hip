@@ -288,11 +288,8 @@ msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restr
   return st1 != MSGPM_OK ? st1 : st0;
 }
 
+// A pass of half-sweeps; a restricted pass reads the lists built before it.
 msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
-  if (restricted) {
-    msgpm_status st = run_lists(c);
-    if (st != MSGPM_OK) return st;
-  }
   for (int it = 0; it < c.P.iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       msgpm_status st = run_halfsweep(c, colour, it, slot, restricted);
@@ -340,6 +337,7 @@ msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* 
   msgpm_status st = open_ctx(p, d_ws, stream, &c);
   if (st != MSGPM_OK) return st;
   if (mode < 0 || mode > 2) return fail(MSGPM_E_INVALID, "mode must be 0, 1 or 2");
+  if (mode == 1 && (st = run_lists(c)) != MSGPM_OK) return st;  // mode 1 reads the unassigned pixels' lists
   return check(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, mode, c.s); }), "eval_cost");
 }
 
@@ -446,6 +444,8 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
     RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
     if (c.P.cues & MSGPM_FLAG_CUE_UNIQUE) RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_unique(c.P, c.w, c.s); }), "unique");
     RUN(timed(MSGPM_T_NNF_UPDATE, c.s, [&] { return launch_nnf_update(c.P, c.w, l, c.s); }), "nnf_update");
+    // the unassigned pixels' lists serve the cost refresh and the whole restricted pass
+    if ((st = run_lists(c)) != MSGPM_OK) return st;
     RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 1, c.s); }), "eval_cost");
     if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
   }
@@ -571,9 +571,10 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
     if (P.cues & MSGPM_FLAG_CUE_UNIQUE)
       for (int phase = 0; phase < 4; ++phase) add(BK_UNIQUE, MSGPM_T_FB, phase);
     add(BK_NNF_UPDATE, MSGPM_T_NNF_UPDATE, l);
-    add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
     add(BK_ZERO_ACTIVE, MSGPM_T_PM_LIST);
     for (int colour = 0; colour < 2; ++colour) add(BK_ACTIVE_LIST, MSGPM_T_PM_LIST, colour);
+    add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 1);
+    add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
     for (int it = 0; it < P.iters; ++it)
       for (int colour = 0; colour < 2; ++colour) {
         add(BK_PM_RESTRICTED, MSGPM_T_PM_RESTRICTED, colour, it, l + 1, 1);

@@ -347,14 +347,33 @@ __device__ __forceinline__ void eval_cost_body(const DevParams& P, const Ws& w, 
   const int g = lane / G, j = lane - g * G, base = g * G;
   const int dir = bk.y;
   const int W = P.W, H = P.H;
-  const long long i = ((long long)xcd_remap(bk.x, bk.nx) * (kBlock / kWave) + wave) * NG + g;
-  bool act = g < NG && i < (long long)W * H;
-  const int p = act ? (int)i : 0, x = p % W, y = p / W;
+  bool act;
+  int p;
   int label = -1;
-  if (act && mode == 1) {
-    act = w.win[dir][p] < 0;
-    label = w.hlabel[dir][p];
-  } else if (act && mode == 2) {
+  if (mode == 1) {
+    // the unassigned pixels, from the restricted pass's lists (both colours):
+    // identity patches over the back lists (no region plane), distorted ones
+    // over the front lists; each colour takes its own run of workgroups
+    constexpr unsigned per = NG * (kBlock / kWave);
+    const unsigned c0 = w.act_count[2 * (2 * dir) + (IDENT ? 1 : 0)];
+    const unsigned c1 = w.act_count[2 * (2 * dir + 1) + (IDENT ? 1 : 0)];
+    const int nb0 = (int)((c0 + per - 1) / per), nb1 = (int)((c1 + per - 1) / per);
+    if (bk.x >= nb0 + nb1) return;
+    const int colour = bk.x < nb0 ? 0 : 1;
+    const int b = colour ? bk.x - nb0 : bk.x, nb = colour ? nb1 : nb0;
+    const unsigned cnt = colour ? c1 : c0;
+    const long long i = ((long long)xcd_remap(b, nb) * (kBlock / kWave) + wave) * NG + g;
+    act = g < NG && i < (long long)cnt;
+    const unsigned cap = (unsigned)((W + 1) >> 1) * (unsigned)H;
+    p = act ? w.act[2 * dir + colour][IDENT ? cap - 1u - (unsigned)i : (unsigned)i] : 0;
+    label = act && !IDENT ? w.hlabel[dir][p] : -1;
+  } else {
+    const long long i = ((long long)xcd_remap(bk.x, bk.nx) * (kBlock / kWave) + wave) * NG + g;
+    act = g < NG && i < (long long)W * H;
+    p = act ? (int)i : 0;
+  }
+  const int x = p % W, y = p / W;
+  if (act && mode == 2) {
     label = w.win[dir][p];
     act = label >= 0;
   }
@@ -837,9 +856,9 @@ hipError_t launch_pm_lists(const DevParams& P, const Ws& w, hipStream_t s) {
 template <int R, int C, bool FP16, bool IDENT>
 static hipError_t ec_launch(const DevParams& P, const Ws& w, int mode, hipStream_t s) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
-  const long long n = (long long)P.W * P.H;
+  const long long n = (long long)P.W * P.H, half = (long long)((P.W + 1) >> 1) * P.H;
   const long long per = (long long)NG * (kBlock / kWave);
-  const int nb = (int)((n + per - 1) / per);
+  const int nb = mode == 1 ? (int)(2 * ((half + per - 1) / per)) : (int)((n + per - 1) / per);
   hipLaunchKernelGGL((k_eval_cost<R, C, FP16, IDENT>), dim3(nb, 2), dim3(kBlock), 0, s, P, w, mode);
   return hipGetLastError();
 }
@@ -854,6 +873,10 @@ static hipError_t dispatch_pm(const DevParams& P, const Ws& w, int colour, int i
 template <int R, int C, bool FP16>
 static hipError_t dispatch_ec(const DevParams& P, const Ws& w, int mode, hipStream_t s) {
   if (mode == 0) return ec_launch<R, C, FP16, true>(P, w, mode, s);
+  if (mode == 1) {
+    hipError_t e = ec_launch<R, C, FP16, true>(P, w, mode, s);
+    if (e != hipSuccess) return e;
+  }
   return ec_launch<R, C, FP16, false>(P, w, mode, s);
 }
 
@@ -926,12 +949,13 @@ hipError_t launch_batched_pm(int kind, const DevParams& P0, const PairDesc* pd, 
 
 // Workgroups of the PatchMatch-side kernels for one pair (the single-pair
 // launchers' grids).
-int pm_batch_blocks(int kind, const DevParams& P) {
+int pm_batch_blocks(int kind, const DevParams& P, const int* a) {
   const int G = 2 * P.r + 1, NG = kWave / G, per = NG * (kBlock / kWave);
   const long long half = (long long)((P.W + 1) >> 1) * P.H;
   switch (kind) {
     case BK_EVAL_COST_IDENT:
     case BK_EVAL_COST_PLANE:
+      if (a && a[0] == 1) return (int)(2 * ((half + per - 1) / per));  // both colours' lists
       return (int)(((long long)P.W * P.H + per - 1) / per);
     case BK_ZERO_ACTIVE:
       return 1;

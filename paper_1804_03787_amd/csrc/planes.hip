@@ -813,11 +813,16 @@ __device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ransac(DevParams P, Ws w, int level, int stage) {
+// Held to 168 VGPRs (3 waves per SIMD, a few registers of the DLT spilled): the
+// scoring loop needs the waves to hide FP64 latency more than the hypothesis
+// generation needs the registers.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_ransac(DevParams P, Ws w, int level,
+                                                                                         int stage) {
   ransac_body(P, w, blk_here(), level, stage);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_ransac(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_ransac(const PairDesc* __restrict__ pd,
+                                                                                          const Item* __restrict__ it, int n) {
   int i;
   Blk bk;
   if (!batch_blk(it, n, i, bk)) return;
@@ -1320,7 +1325,7 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
   return hipGetLastError();
 }
 
-int pm_batch_blocks(int kind, const DevParams& P);
+int pm_batch_blocks(int kind, const DevParams& P, const int* a);
 
 int batch_grid_y(int kind) {
   return (kind == BK_INIT_PLANES || kind == BK_ZERO_ACTIVE || kind == BK_FILL_CLEAR || kind == BK_HEQ_CLEAR) ? 1 : 2;
@@ -1352,7 +1357,7 @@ int batch_blocks(int kind, const DevParams& P, const int* a) {
     case BK_PM_INIT:
     case BK_PM_RESTRICTED:
     case BK_PM_RESTRICTED_IDENT:
-      return pm_batch_blocks(kind, P);
+      return pm_batch_blocks(kind, P, a);
     default:
       return px;
   }
