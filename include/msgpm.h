@@ -321,6 +321,13 @@ msgpm_status msgpm_server_submit(msgpm_server* server, const msgpm_params* p, co
 /* *pending: pairs queued or still being launched after this round. */
 msgpm_status msgpm_server_step(msgpm_server* server, void* d_scratch, void* stream, int* pending);
 msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done);
+/* Cancels a pair.  Queued: removed at once, its ticket retired (*retired = 1,
+   may be NULL).  In flight: it takes part in no further round; the next
+   msgpm_server_step marks the end of the work already enqueued for it, after
+   which msgpm_server_poll reports it done (its outputs are then undefined) and
+   its budget is released; its buffers may be written until then.  Fully
+   launched: no effect, the pair completes normally. */
+msgpm_status msgpm_server_cancel(msgpm_server* server, uint64_t ticket, int* retired);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing.  While enabled, the library records a pair of HIP events on

@@ -786,6 +786,7 @@ struct Slot {
   uint64_t bytes = 0;           // workspace footprint counted against the budget
   hipEvent_t done = nullptr;    // recorded after the pair's last launch
   int state = 0;                // 0 queued, 1 active, 2 all launched, 3 finished
+  bool cancelled = false;       // active pair to be dropped at the next round
 };
 
 }  // namespace
@@ -928,6 +929,27 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   msgpm_status st;
   server_retire(sv);
+  // cancelled in-flight pairs leave the round; their budget returns once the
+  // work already enqueued for them has passed
+  {
+    std::vector<Slot*> keep;
+    for (Slot* q : sv->active) {
+      if (!q->cancelled) {
+        keep.push_back(q);
+        continue;
+      }
+      if (sv->events.empty()) {
+        hipEvent_t e;
+        if ((st = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != MSGPM_OK) return st;
+        sv->events.push_back(e);
+      }
+      q->done = sv->events.back();
+      sv->events.pop_back();
+      if ((st = check(hipEventRecord(q->done, s), "event")) != MSGPM_OK) return st;
+      q->state = 2;
+    }
+    sv->active.swap(keep);
+  }
   // admission: first come, first served, while the budget and the slot count allow
   while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
          sv->in_use + sv->queue.front()->bytes <= sv->budget) {
@@ -1025,6 +1047,28 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   }
   sv->active.swap(still);
   if (pending) *pending = (int)(sv->active.size() + sv->queue.size());
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_cancel(msgpm_server* sv, uint64_t ticket, int* retired) {
+  if (!sv) return fail(MSGPM_E_INVALID, "server is NULL");
+  if (retired) *retired = 0;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto f = sv->slots.find(ticket);
+  if (f == sv->slots.end()) return fail(MSGPM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Slot* q = f->second;
+  if (q->state == 0) {  // still queued: nothing was enqueued for it
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+      if (*it == q) {
+        sv->queue.erase(it);
+        break;
+      }
+    sv->slots.erase(f);
+    delete q;
+    if (retired) *retired = 1;
+  } else if (q->state == 1) {
+    q->cancelled = true;
+  }
   return MSGPM_OK;
 }
 

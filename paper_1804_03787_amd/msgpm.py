@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_server_submit": [vp, P] + [vp] * 9 + [pu64],
             "msgpm_server_step": [vp, vp, vp, ctypes.POINTER(i)],
             "msgpm_server_poll": [vp, u64, ctypes.POINTER(i)],
+            "msgpm_server_cancel": [vp, u64, ctypes.POINTER(i)],
         }.items():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = ctypes.c_int
@@ -405,6 +406,16 @@ class Server:
         d = ctypes.c_int()
         _call("msgpm_server_poll", self.h, int(ticket), ctypes.byref(d))
         return bool(d.value)
+
+    def cancel(self, ticket: int) -> bool:
+        """Cancels a pair; True if it was still queued and is gone already (an
+        in-flight pair is reported done by poll once its enqueued work passed;
+        its outputs are then undefined)."""
+        r = ctypes.c_int()
+        _call("msgpm_server_cancel", self.h, int(ticket), ctypes.byref(r))
+        if r.value:
+            self.jobs.pop(ticket, None)
+        return bool(r.value)
 
     def result(self, ticket: int):
         """(pair, [flow0, flow1], [occ0, occ1]) of a finished ticket; forgets it."""

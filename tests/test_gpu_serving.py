@@ -85,3 +85,45 @@ def test_serving_admission_by_budget_and_errors():
         srv.submit(msgpm.Pair(pr.shape[1], pr.shape[0], **other), pr.frame1, pr.frame2)
     small.close()
     srv.close()
+
+
+def test_serving_cancel_queued_and_in_flight():
+    """A queued pair cancelled before admission is gone at once; an in-flight
+    pair cancelled after a few rounds leaves the rounds, is reported done and
+    returns its budget; the pair left running still matches its lone solve."""
+    msgpm = _need_gpu()
+    scenes = _scenes()[:3]
+    alone = []
+    for pr, p in scenes:
+        g = msgpm.Pair(pr.shape[1], pr.shape[0], **p)
+        alone.append(_outputs(g, *g.solve(pr.frame1, pr.frame2)))
+    pairs = [msgpm.Pair(pr.shape[1], pr.shape[0], **p) for pr, p in scenes]
+    srv = msgpm.Server(hbm_budget=1 << 34, max_active=2)
+    ts = [srv.submit(g, pr.frame1, pr.frame2) for g, (pr, _) in zip(pairs, scenes)]
+    assert srv.cancel(ts[2])            # third pair never admitted (two slots)
+    with pytest.raises(msgpm.MsgpmError):
+        srv.poll(ts[2])
+    for _ in range(5):
+        srv.step()
+    assert not srv.cancel(ts[1])        # in flight: leaves at the next round
+    done = {}
+    for _ in range(100000):
+        pend = srv.step()
+        for t in ts[:2]:
+            if t not in done and srv.poll(t):
+                done[t] = True
+        if len(done) == 2:
+            break
+    assert len(done) == 2 and pend == 0
+    g, flows, occs = srv.result(ts[0])
+    _same(alone[0], _outputs(g, flows, occs))
+    srv.result(ts[1])
+    # the cancelled pairs' budget is free again: the third pair now runs alone
+    t = srv.submit(pairs[2], scenes[2][0].frame1, scenes[2][0].frame2)
+    for _ in range(100000):
+        srv.step()
+        if srv.poll(t):
+            break
+    g, flows, occs = srv.result(t)
+    _same(alone[2], _outputs(g, flows, occs))
+    srv.close()
