@@ -387,6 +387,24 @@ def main() -> int:
 
     value = W * H / (ms_per_step / 1e3) / 1e6
 
+    # not the headline: the same steps with the frames coming from pinned host
+    # memory and the flow and masks going back to it (PCIe included)
+    f1h, f2h = torch.from_numpy(pair.frame1).pin_memory(), torch.from_numpy(pair.frame2).pin_memory()
+    flows_h = [torch.empty((H, W, 2), dtype=torch.float32).pin_memory() for _ in range(2)]
+    occs_h = [torch.empty((H, W), dtype=torch.uint8).pin_memory() for _ in range(2)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(args.steps):
+        f1.copy_(f1h, non_blocking=True)
+        f2.copy_(f2h, non_blocking=True)
+        g.solve(f1, f2, out=(flows, occs), graph=use_graph)
+        for d in range(2):
+            flows_h[d].copy_(flows[d], non_blocking=True)
+            occs_h[d].copy_(occs[d], non_blocking=True)
+    torch.cuda.synchronize()
+    pcie_ms = (time.perf_counter() - tp) * 1e3 / args.steps
+    print(f"bench: with host transfers {pcie_ms:.2f} ms/step", file=sys.stderr, flush=True)
+
     # evaluations of the last step (every step is identical: same inputs and seed);
     # a candidate rejected early by its partial sum counts for the rows it computed
     cnt = g.counters()
@@ -444,6 +462,13 @@ def main() -> int:
                    "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill, "histeq": bool(args.histeq)},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
+        # the initial pass alone: its evaluations over its kernel time, beside the
+        # count without skipped duplicates (every pixel, 4 neighbours + every radius)
+        "patch_evals_per_s_initial_pass": round(ev["pm_init"] / (kernel_ms["pm_init"] * 1e-3), 1)
+        if kernel_ms.get("pm_init") else None,
+        "evals_upper_bound_initial_pass": PARAMS["iters"] * W * H * 2 * (4 + (max(W, H)).bit_length()),
+        "pcie_inclusive_ms_per_step": round(pcie_ms, 3),
+        "pcie_inclusive_mpix_s": round(W * H / (pcie_ms / 1e3) / 1e6, 4),
         "evals_per_step": {**ev, **{k + "_full_equiv": round(v) for k, v in full.items()}},
         "kernel_ms_per_step": {k: round(v, 3) for k, v in kernel_ms.items()},
         "occluded_fraction_dir0": round(occ0, 4),

@@ -492,6 +492,10 @@ __device__ inline void score_batch(const double* aux, const unsigned long long* 
   }
 }
 
+// UMAX: points per lane of the scoring loop for the largest windows (8 for
+// windows of more than 512 points, whose scoring dominates; 4 otherwise, which
+// keeps the hypothesis generation of small windows from spilling more).
+template <int UMAX>
 __device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk bk, int level, int stage) {
   extern __shared__ double smem_d[];
   __shared__ int s_wave[kBlock / kWave];
@@ -601,8 +605,10 @@ __device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk
       score_batch<1>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
     else if (n <= 2 * kWave)
       score_batch<2>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
-    else
+    else if (UMAX < 8 || n <= 8 * kWave)
       score_batch<4>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
+    else
+      score_batch<UMAX>(aux, s_gmask, s_cnt, ngroups, src, dst, n, tau2, wave, lane);
     __syncthreads();
     unsigned long long key = ok ? (((unsigned long long)s_cnt[t] << 32) | (0xffffffffu - (unsigned)h)) : 0ull;
 #pragma unroll
@@ -816,18 +822,31 @@ __device__ __forceinline__ void ransac_body(const DevParams& P, const Ws& w, Blk
 // Held to 168 VGPRs (3 waves per SIMD, a few registers of the DLT spilled): the
 // scoring loop needs the waves to hide FP64 latency more than the hypothesis
 // generation needs the registers.
+template <int UMAX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_ransac(DevParams P, Ws w, int level,
                                                                                          int stage) {
-  ransac_body(P, w, blk_here(), level, stage);
+  ransac_body<UMAX>(P, w, blk_here(), level, stage);
 }
 
+template <int UMAX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_ransac(const PairDesc* __restrict__ pd,
                                                                                           const Item* __restrict__ it, int n) {
   int i;
   Blk bk;
   if (!batch_blk(it, n, i, bk)) return;
   const Item& I = it[i];
-  ransac_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+  ransac_body<UMAX>(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+}
+
+// Windows of more than this many points take the 8-points-per-lane scoring.
+constexpr size_t kRansacWide = 8 * kWave;
+
+template <class K>
+static hipError_t ransac_lds(K kernel, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  // windows above 64x64 keep their point list in more than 64 KB of LDS
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1213,6 +1232,9 @@ __global__ __launch_bounds__(kBlock) void kb_finalize(const PairDesc* __restrict
 // ---------------------------------------------------------------------------
 static dim3 pixel_grid(const DevParams& P) { return dim3((P.W * P.H + kBlock - 1) / kBlock, 2); }
 
+// Points of the largest window a RANSAC launch with this dynamic LDS serves.
+static size_t ransac_points(size_t lds) { return (lds - kAuxDoubles * sizeof(double)) / (2 * sizeof(uint32_t)); }
+
 size_t ransac_smem_bytes(const DevParams& P, int level) {
   const int B = P.block[level];
   const int bw = B < P.W ? B : P.W, bh = B < P.H ? B : P.H;
@@ -1222,13 +1244,15 @@ size_t ransac_smem_bytes(const DevParams& P, int level) {
 
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s) {
   const size_t sm = ransac_smem_bytes(P, level);
-  if (sm > 64 * 1024) {
-    // windows above 64x64 keep their point list in more than 64 KB of LDS
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ransac),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
+  const dim3 grid(P.nbx[level] * P.nby[level], 2);
+  hipError_t e;
+  if (ransac_points(sm) > kRansacWide) {
+    if ((e = ransac_lds(&k_ransac<8>, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ransac<8>, grid, dim3(kBlock), sm, s, P, w, level, stage);
+  } else {
+    if ((e = ransac_lds(&k_ransac<4>, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ransac<4>, grid, dim3(kBlock), sm, s, P, w, level, stage);
   }
-  hipLaunchKernelGGL(k_ransac, dim3(P.nbx[level] * P.nby[level], 2), dim3(kBlock), sm, s, P, w, level, stage);
   return hipGetLastError();
 }
 
@@ -1284,14 +1308,17 @@ hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, i
                                  hipStream_t s) {
   const dim3 grid(total, batch_grid_y(kind)), block(kBlock);
   switch (kind) {
-    case BK_RANSAC:
-      if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&kb_ransac),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    case BK_RANSAC: {
+      hipError_t e;
+      if (ransac_points(lds) > kRansacWide) {
+        if ((e = ransac_lds(&kb_ransac<8>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(kb_ransac<8>, grid, block, lds, s, pd, it, n);
+      } else {
+        if ((e = ransac_lds(&kb_ransac<4>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(kb_ransac<4>, grid, block, lds, s, pd, it, n);
       }
-      hipLaunchKernelGGL(kb_ransac, grid, block, lds, s, pd, it, n);
       break;
+    }
     case BK_ASSIGN:
       hipLaunchKernelGGL(kb_assign, grid, block, 0, s, pd, it, n);
       break;
