@@ -89,6 +89,27 @@ def test_features_bitexact(C, fp16, histeq):
         assert np.array_equal(ref.view(np.uint32), got.view(np.uint32))
 
 
+def test_histeq_features_edge_frames():
+    """Equalisation on frames that take its special paths: a single-level frame
+    (left as it is), a frame with black and negative pixels (value <= 0) and
+    values above 1 (clamped levels); features bit-exact against the oracle."""
+    msgpm = _need_gpu()
+    rng = np.random.default_rng(61)
+    W, H = 45, 31
+    flat = np.full((H, W, 3), 0.4, np.float32)
+    flat[..., 2] = 0.1
+    odd = rng.random((H, W, 3)).astype(np.float32) * 1.6 - 0.2
+    odd[:5, :7] = 0.0
+    odd[10:12, 3:9] = -0.05
+    for C in (3, 5):
+        g = msgpm.Pair(W, H, **_gpu_params(dict(C=C, blocks=(16,), histeq=True)))
+        g.set_features(flat, odd)
+        for f, frame in enumerate((flat, odd)):
+            ref = oracle.features(oracle.histeq(frame), C=C)
+            assert np.array_equal(g.features(f).view(np.uint32), ref.view(np.uint32)), (C, f)
+    assert np.array_equal(oracle.histeq(flat), flat)
+
+
 def test_init_nnf_bitexact_and_given_nnf_clamped():
     msgpm = _need_gpu()
     pair = synth.tiny_pair(0)
