@@ -49,6 +49,15 @@ def _ragged_pair():
     return synth.render([bg, fg], W, H, rng)
 
 
+def _two_layer_pair(W, H, seed):
+    """A zoomed and rotated background with one translated foreground quad."""
+    rng = np.random.default_rng(seed)
+    bg = synth.Layer(H=synth.similarity_about(W / 2, H / 2, 1.02, 2.0, 4.0, -3.0))
+    fg = synth.Layer(H=synth.translation(-6, 4),
+                     poly=np.array([[0.2 * W, 0.2 * H], [0.55 * W, 0.25 * H], [0.5 * W, 0.7 * H], [0.25 * W, 0.65 * H]]))
+    return synth.render([bg, fg], W, H, rng)
+
+
 CASES = {
     "tiny_c5": (lambda: synth.tiny_pair(0), TINY_PARAMS),
     "tiny_c3": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, C=3, grad_weight=0.0)),
@@ -64,6 +73,10 @@ CASES = {
     "tiny_fill": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fill_sweeps=64)),
     # frames equalised in HSV value before the features
     "tiny_histeq": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, histeq=True)),
+    # 128-pixel windows (as the fourth level of 2048-wide frames): point lists of
+    # up to 16384 points, more than 64 KB of LDS, 8 points per lane in the scoring
+    "big_windows": (lambda: _two_layer_pair(224, 160, 41),
+                    dict(C=5, r=3, blocks=(128, 64), iters=3, hyps=128, tau=1.0, eps=0.1, tau_fb=1.0, seed=4)),
     # the paper's own preset: two levels of 81 and 41 pixel windows (strides 40
     # and 20), 7x7 patches over RGB
     "paper_preset": (lambda: synth.planar_pair(200, 144, seed=11, scale=0.08),
