@@ -267,6 +267,22 @@ hipError_t aux_stream(Aux** out) {
   return hipSuccess;
 }
 
+// Runs on_second on the calling thread's second stream beside on_caller on s:
+// forked from s and joined back into it by events, also when a launch fails.
+template <class A, class B>
+msgpm_status side_by_side(hipStream_t s, A&& on_caller, B&& on_second) {
+  Aux* a = nullptr;
+  msgpm_status st;
+  if ((st = check(aux_stream(&a), "second stream")) != MSGPM_OK) return st;
+  if ((st = check(hipEventRecord(a->fork, s), "fork")) != MSGPM_OK) return st;
+  if ((st = check(hipStreamWaitEvent(a->s, a->fork, 0), "fork")) != MSGPM_OK) return st;
+  const msgpm_status st1 = on_second(a->s);
+  const msgpm_status st0 = on_caller(s);
+  if ((st = check(hipEventRecord(a->join, a->s), "join")) != MSGPM_OK) return st;
+  if ((st = check(hipStreamWaitEvent(s, a->join, 0), "join")) != MSGPM_OK) return st;
+  return st1 != MSGPM_OK ? st1 : st0;
+}
+
 msgpm_status run_lists(const Ctx& c) {
   return check(timed(MSGPM_T_PM_LIST, c.s, [&] { return launch_pm_lists(c.P, c.w, c.s); }), "pm_list");
 }
@@ -275,17 +291,15 @@ msgpm_status run_lists(const Ctx& c) {
 msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted) {
   if (!restricted)
     return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_halfsweep");
-  msgpm_status st;
-  Aux* a = nullptr;
-  if ((st = check(aux_stream(&a), "second stream")) != MSGPM_OK) return st;
-  if ((st = check(hipEventRecord(a->fork, c.s), "fork")) != MSGPM_OK) return st;
-  if ((st = check(hipStreamWaitEvent(a->s, a->fork, 0), "fork")) != MSGPM_OK) return st;
-  // fork: identity patches on the second stream, distorted ones on the caller's; always joined
-  msgpm_status st1 = check(timed(MSGPM_T_PM_RESTRICTED_IDENT, a->s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, a->s); }), "pm_restricted");
-  msgpm_status st0 = check(timed(MSGPM_T_PM_RESTRICTED, c.s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_restricted");
-  if ((st = check(hipEventRecord(a->join, a->s), "join")) != MSGPM_OK) return st;
-  if ((st = check(hipStreamWaitEvent(c.s, a->join, 0), "join")) != MSGPM_OK) return st;
-  return st1 != MSGPM_OK ? st1 : st0;
+  // distorted patches on the caller's stream, identity patches on the second one
+  return side_by_side(
+      c.s,
+      [&](hipStream_t s) {
+        return check(timed(MSGPM_T_PM_RESTRICTED, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, s); }), "pm_restricted");
+      },
+      [&](hipStream_t s) {
+        return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, s); }), "pm_restricted");
+      });
 }
 
 // A pass of half-sweeps; a restricted pass reads the lists built before it.
@@ -731,12 +745,15 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
   }
   const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
   const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
-  for (size_t k = 0; k < plan.steps.size(); ++k) {
+  auto step = [&](size_t k, hipStream_t q) {
     const BatchStep& bs = plan.steps[k];
-    st = check(timed(bs.timer, s, [&] { return launch_batched(bs.kind, P[0], pd, it + k * n, n, plan.total[k], plan.lds[k], s); }),
-               "batched launch");
-    if (st != MSGPM_OK) return st;
-  }
+    return check(timed(bs.timer, q, [&] { return launch_batched(bs.kind, P[0], pd, it + k * n, n, plan.total[k], plan.lds[k], q); }),
+                 "batched launch");
+  };
+  // one launch per step on the caller's stream: with many pairs per launch the two
+  // restricted kinds gain nothing from running side by side (measured)
+  for (size_t k = 0; k < plan.steps.size(); ++k)
+    if ((st = step(k, s)) != MSGPM_OK) return st;
   return MSGPM_OK;
 }
 
@@ -1022,12 +1039,13 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
   const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
   DevParams P0 = sv->active[0]->P;
-  for (const Group& gr : groups) {
+  auto launch_group = [&](const Group& gr, hipStream_t q) {
     const BatchStep& bs = sv->active[order[gr.first]]->steps[sv->active[order[gr.first]]->cursor];
-    st = check(timed(bs.timer, s, [&] { return launch_batched(gr.kind, P0, pd, it + gr.first, gr.count, gr.total, gr.lds, s); }),
-               "batched launch");
-    if (st != MSGPM_OK) return st;
-  }
+    return check(timed(bs.timer, q, [&] { return launch_batched(gr.kind, P0, pd, it + gr.first, gr.count, gr.total, gr.lds, q); }),
+                 "batched launch");
+  };
+  for (const Group& gr : groups)
+    if ((st = launch_group(gr, s)) != MSGPM_OK) return st;
   // advance; pairs whose last step was launched get their completion event
   std::vector<Slot*> still;
   for (Slot* q : sv->active) {
