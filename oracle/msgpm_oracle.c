@@ -9,8 +9,11 @@
  *   Sec. 3.1.3 Eq. 3-4   plane-distortion compensation, truncated loss, overlap rule
  *   Sec. 3.2             residual-region second stage
  *   Sec. 3.3, Alg. 1     multi-scale loop, merge priority, NNF update, restricted PatchMatch
- *   Sec. 3.4             forward-backward plane symmetry, occlusion = no plane
+ *   Sec. 3.4             forward-backward plane symmetry, occlusion = no plane,
+ *                        the many-to-one and RANSAC/colour-overlap cues
+ *   Sec. 3.4.1           filling by homography-model propagation
  *   Sec. 4               experiment set-up (PatchMatch init, levels, FB per level)
+ *   Sec. 4.2             histogram equalisation of the frames in HSV
  * PatchMatch itself (propagation + random search) is the method of Barnes et al.
  * 2009 that the paper builds on (Sec. 1, Sec. 3.1).
  *
