@@ -332,8 +332,8 @@ def main() -> int:
     ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs the hot path on one GPU only; --gpus {args.gpus} is not supported "
-              "(pairs are independent, so more GPUs would run more pairs; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the pipeline runs on one GPU; --gpus {args.gpus} is not supported "
+              "(frame pairs are independent, so more GPUs would serve more pairs side by side)", file=sys.stderr)
         return 2
     if args.batched:
         return run_batched(args)
