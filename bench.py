@@ -228,8 +228,13 @@ def run_serving(args) -> int:
         torch.cuda.synchronize()
         start = time.perf_counter()
         k = 0
+        shown = start
         while k < len(reqs) or out:
             now = time.perf_counter() - start
+            if time.perf_counter() - shown > 20.0:
+                shown = time.perf_counter()
+                print(f"bench: serving {now:.0f} s: {k} of {len(reqs)} submitted, {len(lat)} done",
+                      file=sys.stderr, flush=True)
             while k < len(reqs) and reqs[k][0] <= now:
                 t, c, j = reqs[k]
                 a, b = frames[(c, j)]
@@ -252,8 +257,12 @@ def run_serving(args) -> int:
         lat = []
         torch.cuda.synchronize()
         start = time.perf_counter()
+        shown = start
         for t, c, j in reqs:
             now = time.perf_counter() - start
+            if time.perf_counter() - shown > 20.0:
+                shown = time.perf_counter()
+                print(f"bench: one at a time {now:.0f} s: {len(lat)} of {len(reqs)} done", file=sys.stderr, flush=True)
             if now < t:
                 time.sleep(t - now)
             a, b = frames[(c, j)]
