@@ -433,10 +433,10 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const PairDesc* __restric
 // Group costs of NB identity-patch targets: each lane walks its column once,
 // issuing the loads of all NB candidates per tap; every candidate is summed in
 // the same order as a lone evaluation.
-#ifndef MSGPM_IDENT_ROWS
-#define MSGPM_IDENT_ROWS 1
-#endif
-constexpr int kIdentRows = MSGPM_IDENT_ROWS;  // tap rows per load chunk of identity-patch batches
+// Tap rows per load chunk of identity-patch batches: one (measured on MI355X, two
+// or three rows per chunk take the kernel to 256 VGPRs and lose more than the
+// longer chunks gain).
+constexpr int kIdentRows = 1;
 
 template <int R, int C, bool FP16, int NB>
 __device__ inline void group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
