@@ -1105,9 +1105,11 @@ void orc_nnf_update(orc_pair* S, int dir, int level) {
         double qx, qy;
         if (orc_project(H_of(S, j), x, y, &qx, &qy)) {
           if (S->pflag[dir] && (near_half(qx) || near_half(qy))) S->pflag[dir][p] |= ORC_F_ROUND;
-          int rx = clampi((int)floor(qx + 0.5), 0, W - 1);
-          int ry = clampi((int)floor(qy + 0.5), 0, H - 1);
-          S->nnf[dir][p] = pack_off(rx - x, ry - y);
+          /* round, then clamp (reading R13), the clamp taken in FP64 so that no
+             projection is converted to int out of range */
+          const double fx = fmin(fmax(floor(qx + 0.5), 0.0), (double)(W - 1));
+          const double fy = fmin(fmax(floor(qy + 0.5), 0.0), (double)(H - 1));
+          S->nnf[dir][p] = pack_off((int)fx - x, (int)fy - y);
         }
       }
       int xlo, xhi;

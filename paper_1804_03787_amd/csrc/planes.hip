@@ -1151,9 +1151,10 @@ __device__ __forceinline__ void nnf_update_body(const DevParams& P, const Ws& w,
   if (j >= 0) {
     double qx, qy;
     if (project(w.planes[j].H, x, y, qx, qy)) {
-      const int rx = clampi((int)floor(qx + 0.5), 0, W - 1);
-      const int ry = clampi((int)floor(qy + 0.5), 0, Hh - 1);
-      w.nnf[dir][p] = pack_off(rx - x, ry - y);
+      // round, then clamp in FP64: no projection is converted to int out of range
+      const double fx = fmin(fmax(floor(qx + 0.5), 0.0), (double)(W - 1));
+      const double fy = fmin(fmax(floor(qy + 0.5), 0.0), (double)(Hh - 1));
+      w.nnf[dir][p] = pack_off((int)fx - x, (int)fy - y);
     }
   }
   const int B = P.block[level], nbx = P.nbx[level], nby = P.nby[level];

@@ -1087,3 +1087,56 @@ def test_histeq_keeps_hue_and_saturation():
     flat = np.full((8, 9, 3), 0.25, np.float32)
     flat[..., 1] = 0.1
     assert np.array_equal(oracle.histeq(flat), flat)
+
+
+# --------------------------------------------------------------------------
+# NNF update and region plane
+# --------------------------------------------------------------------------
+
+def test_nnf_update_rounds_half_up_and_picks_region_plane():
+    """Assigned pixels move to where their plane sends them, rounded half up
+    and clamped into the frame (a translation by (0.5, -1.5) gives the offset
+    (1, -1), which rounding half to even would not); unassigned pixels keep
+    their offset.  The region plane of every pixel is, among the valid planes
+    of both stages whose window contains it, the one with the largest count,
+    ties to stage 1 and then to the lower window; with none the old label
+    stays."""
+    W, H = 48, 32
+    pair = synth.smooth_pair(W, H, seed=71)
+    o = oracle.Oracle(pair.frame1, pair.frame2, C=3, r=2, grad_weight=0.0, blocks=(16,))
+    rng = np.random.default_rng(72)
+    k0 = o.plane_index(0, 0, 1, 0)
+    o.pH[k0] = synth.translation(0.5, -1.5).ravel()
+    assigned = rng.random(W * H) < 0.7
+    old = oracle.pack(rng.integers(-5, 6, W * H), rng.integers(-5, 6, W * H))
+    o.set_nnf(0, old)
+    old = o.nnf[0].copy()        # as stored: targets clamped into the frame
+    o.win[0][:] = np.where(assigned, k0, -1)
+    nwin = o.block_grid(0)[0] * o.block_grid(0)[1]
+    recs = [o.plane_index(0, 0, st, b) for st in (1, 2) for b in range(nwin)]
+    for k in recs:
+        o.pinfo[k, PI["valid"]] = int(rng.random() < 0.5)
+        o.pinfo[k, PI["count"]] = int(rng.integers(5, 9))   # few values: many ties
+    o.hlabel[0][:] = -7
+    o.nnf_update(0, 0)
+    ys, xs = np.divmod(np.arange(W * H), W)
+    ex = np.where(xs == W - 1, 0, 1)
+    ey = np.where(ys == 0, 0, -1)
+    dx, dy = oracle.unpack(o.nnf[0])
+    odx, ody = oracle.unpack(old)
+    assert np.array_equal(dx, np.where(assigned, ex, odx))
+    assert np.array_equal(dy, np.where(assigned, ey, ody))
+    expect = np.full(W * H, -7)
+    for p in range(W * H):
+        best, bestc = -7, -1
+        for k in recs:           # stage 1 windows first, each stage in window order
+            I = o.pinfo[k]
+            if not I[PI["valid"]]:
+                continue
+            if not (I[PI["x0"]] <= xs[p] < I[PI["x0"]] + I[PI["bw"]] and I[PI["y0"]] <= ys[p] < I[PI["y0"]] + I[PI["bh"]]):
+                continue
+            if I[PI["count"]] > bestc:
+                best, bestc = k, I[PI["count"]]
+        expect[p] = best
+    assert np.array_equal(o.hlabel[0], expect)
+    assert (expect == -7).any() and (expect != -7).any()
