@@ -16,6 +16,8 @@ tests cover single steps of each kind rather than the whole pipeline:
     identity-patch kernel over those without), and the outputs; a third form
     (scene seed 2) adds occlusion cues 2 and 3 and the filling.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -172,3 +174,64 @@ def test_full_size_fp16_storage_against_fp32_form():
     print(f"full size, FP16 storage vs FP32 form: mean flow delta {delta:.4f} px, EPE to ground truth "
           f"{epe16:.4f} vs {epe32:.4f} px, occlusion agreement {agree:.4f}")
     assert abs(epe16 - epe32) < 0.05 and agree > 0.95
+
+
+def _project(Hm, x, y):
+    qx, qy = ctypes.c_double(), ctypes.c_double()
+    h = np.ascontiguousarray(Hm, dtype=np.float64).reshape(9)
+    ok = oracle.lib().orc_project(h.ctypes.data_as(ctypes.c_void_p), float(x), float(y), ctypes.byref(qx),
+                                  ctypes.byref(qy))
+    return bool(ok), qx.value, qy.value
+
+
+def test_full_size_graph_solve_sampled_outputs():
+    """The whole pipeline at full size, launched as bench.py launches it (one HIP
+    graph per pair, a replay), checked pixel by pixel on a sample: an assigned
+    pixel's flow is its plane's projection (bit for bit), its colour error is
+    below eps^2 and its cost is the oracle's cost of its offset under that
+    plane; an unassigned pixel's flow is its NNF offset and its cost the
+    oracle's cost under its region plane (or the identity)."""
+    msgpm = _need_gpu()
+    pair = _pair(0)
+    g = msgpm.Pair(W, H, **_gpu_params(FULL))
+    f1, f2 = torch.from_numpy(pair.frame1).cuda(), torch.from_numpy(pair.frame2).cuda()
+    out = ([torch.empty((H, W, 2), device="cuda") for _ in range(2)],
+           [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)])
+    for _ in range(2):
+        flows, occs = g.solve(f1, f2, out=out, graph=True)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(pair.frame1, pair.frame2, **FULL)
+    planes = g.planes()
+    rng = np.random.default_rng(77)
+    eps2 = FULL["eps"] ** 2
+    for d in range(2):
+        flow = flows[d].cpu().numpy().reshape(-1, 2)
+        occ = occs[d].cpu().numpy().ravel()
+        win = g.win(d).cpu().numpy()
+        nnf = g.nnf(d).cpu().numpy()
+        cost = g.cost(d).cpu().numpy()
+        hl = g.hlabel(d).cpu().numpy()
+        dx, dy = oracle.unpack(nnf)
+        assigned = np.nonzero(win >= 0)[0]
+        free = np.nonzero(win < 0)[0]
+        assert len(assigned) > 0.5 * W * H and len(free) > 1000
+        for p in np.concatenate([rng.choice(assigned, 200, replace=False), rng.choice(free, 200, replace=False)]):
+            x, y = int(p % W), int(p // W)
+            tx, ty = x + int(dx[p]), y + int(dy[p])
+            j = int(win[p])
+            if j >= 0:
+                Hm = planes["H"][j]
+                ok, qx, qy = _project(Hm, x, y)
+                assert ok and occ[p] == 0
+                assert flow[p, 0] == np.float32(qx - x) and flow[p, 1] == np.float32(qy - y), (d, p)
+                assert o.colour_err(d, x, y, Hm) < eps2
+            else:
+                Hm = planes["H"][hl[p]] if hl[p] >= 0 else None
+                assert occ[p] == 1
+                assert flow[p, 0] == dx[p] and flow[p, 1] == dy[p]
+            ref = o.cost_at(d, x, y, tx, ty, Hm)
+            if not np.isfinite(ref):
+                assert not np.isfinite(cost[p])
+                continue
+            tol = parity.cost_tol(np.array([ref]), FULL["r"], FULL["C"])[0]
+            assert abs(float(cost[p]) - ref) <= tol, (d, p, float(cost[p]), ref)
