@@ -193,16 +193,21 @@ msgpm_status msgpm_init_state(const msgpm_params* p, const int32_t* d_init_nnf0,
                               void* d_ws, void* stream);
 
 /* Recomputes the warped-patch cost of the current offset.  mode 0: every pixel
-   under the identity; mode 1: unassigned pixels under their region plane;
-   mode 2: assigned pixels under their assigned plane. */
+   under the identity; mode 1: unassigned pixels under their region plane (the
+   identity where they have none), over the restricted pass's pixel lists, which
+   this call builds; mode 2: assigned pixels under their assigned plane. */
 msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* stream);
 
 /* One red-black half-sweep of PatchMatch (propagation from the four
    neighbours, then random search; Barnes et al. as used in Sec. 3.1) over the
    pixels with (x + y) % 2 == colour.  restricted = 0: every pixel, identity
    patch; restricted = 1: unassigned pixels only, patches distorted by the region
-   plane, plus the candidate that plane predicts (Sec. 3.3.2).  iter and slot
-   (0 = initial pass, level + 1 = pass after that level) key the random stream. */
+   plane, plus the candidate that plane predicts (Sec. 3.3.2); this call builds
+   the pixel lists, and its two launches (pixels with and without a region
+   plane) run side by side on the caller's stream and a second stream of the
+   calling thread, joined back into the caller's stream before it returns.
+   iter and slot (0 = initial pass, level + 1 = pass after that level) key the
+   random stream. */
 msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, int iter, int slot, int restricted,
                                 void* stream);
 
