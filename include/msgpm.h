@@ -167,7 +167,10 @@ const char* msgpm_last_error(void);
  *                   (occluded, Sec. 3.4), 2 = filled by model propagation
  *                   (no plane of its own: occluded by the same rule, with a
  *                   neighbour's plane flow).
- * The plane table stays in the workspace (layout.planes).
+ * The plane table stays in the workspace (layout.planes).  Work is enqueued
+ * on `stream` and the call returns; the identity-patch half of each restricted
+ * half-sweep runs on a second stream of the calling thread (created on first
+ * use, default priority), forked from and joined back into `stream` by events.
  * ------------------------------------------------------------------------- */
 msgpm_status msgpm_solve(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
                          const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, void* d_ws,
