@@ -73,6 +73,13 @@ CASES = {
     "tiny_fill": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, fill_sweeps=64)),
     # frames equalised in HSV value before the features
     "tiny_histeq": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, histeq=True)),
+    # no plane levels at all: PatchMatch alone, every pixel occluded, an empty
+    # plane table (and a filling with nothing to propagate)
+    "no_levels": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, blocks=(), fill_sweeps=4)),
+    # a frame smaller than the patch and the window (9x7, 9x9 patches, 8-pixel
+    # windows): every gather clamps, one wave holds the whole frame
+    "minimal": (lambda: _two_layer_pair(9, 7, 43),
+                dict(C=5, r=4, blocks=(8,), iters=2, hyps=16, tau=1.0, eps=0.1, tau_fb=1.0, seed=6)),
     # 128-pixel windows (as the fourth level of 2048-wide frames): point lists of
     # up to 16384 points, more than 64 KB of LDS, 8 points per lane in the scoring
     "big_windows": (lambda: _two_layer_pair(224, 160, 41),
