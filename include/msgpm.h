@@ -210,7 +210,14 @@ msgpm_status msgpm_eval_cost(const msgpm_params* p, void* d_ws, int mode, void* 
    plane) run side by side on the caller's stream and a second stream of the
    calling thread, joined back into the caller's stream before it returns.
    iter and slot (0 = initial pass, level + 1 = pass after that level) key the
-   random stream. */
+   random stream.  restricted may carry MSGPM_PM_FRESH: each swept pixel's
+   current cost is then computed first, exactly as msgpm_eval_cost (mode 0
+   for restricted = 0, mode 1 for restricted = 1) would compute it, instead of
+   being read from the workspace; the result equals that refresh followed by
+   the plain half-sweep, over this colour's pixels.  msgpm_solve uses it for
+   the first half-sweep of each colour in every pass.  Any other value of
+   restricted is MSGPM_E_INVALID. */
+#define MSGPM_PM_FRESH 2
 msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, int iter, int slot, int restricted,
                                 void* stream);
 

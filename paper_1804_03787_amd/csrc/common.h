@@ -174,13 +174,15 @@ hipError_t launch_features(const DevParams& P, const Ws& w, const float* rgb, in
 hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
                              hipStream_t s);
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s);
-// initial pass (identity patches over every pixel of the colour)
-hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
+// initial pass (identity patches over every pixel of the colour); fresh: the
+// pixels' current costs are computed in the sweep (the mode-0 cost refresh)
+hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int fresh,
                                hipStream_t s);
-// restricted pass: the pixel lists, then one kernel per list
+// restricted pass: the pixel lists, then one kernel per list; fresh: the
+// listed pixels' current costs are computed in the sweep (the mode-1 refresh)
 hipError_t launch_pm_lists(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
-                                hipStream_t s);
+                                int fresh, hipStream_t s);
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
 hipError_t launch_assign(const DevParams& P, const Ws& w, int level, int stage, int tentative, hipStream_t s);
 hipError_t launch_symmetry(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s);
@@ -203,8 +205,8 @@ enum BatchKind {
   BK_EVAL_COST_PLANE,  // a = {mode 1 or 2}: region-plane cost refresh
   BK_ZERO_ACTIVE,   // one workgroup per item, grid.y = 1
   BK_ACTIVE_LIST,   // a = {colour}
-  BK_PM_INIT,       // a = {colour, iter, slot, 0}
-  BK_PM_RESTRICTED, // a = {colour, iter, slot, 1}: pixels with a region plane
+  BK_PM_INIT,       // a = {colour, iter, slot, 0 | 2 (fresh: cost computed in the sweep)}
+  BK_PM_RESTRICTED, // a = {colour, iter, slot, 1 | 2 (fresh)}: pixels with a region plane
   BK_PM_RESTRICTED_IDENT,  // the same, pixels without one
   BK_RANSAC,        // a = {level, stage}
   BK_ASSIGN,        // a = {level, stage, tentative}

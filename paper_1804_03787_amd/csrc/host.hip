@@ -287,26 +287,34 @@ msgpm_status run_lists(const Ctx& c) {
   return check(timed(MSGPM_T_PM_LIST, c.s, [&] { return launch_pm_lists(c.P, c.w, c.s); }), "pm_list");
 }
 
-// One half-sweep; a restricted one reads the lists run_lists built.
-msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted) {
+// One half-sweep; a restricted one reads the lists run_lists built.  fresh:
+// the swept pixels' current costs are computed in the sweep (the cost refresh
+// of the pass) instead of being read.
+msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted, int fresh) {
   if (!restricted)
-    return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, 0, c.s); }), "pm_halfsweep");
+    return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, fresh, c.s); }), "pm_halfsweep");
   // distorted patches on the caller's stream, identity patches on the second one
   return side_by_side(
       c.s,
       [&](hipStream_t s) {
-        return check(timed(MSGPM_T_PM_RESTRICTED, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, s); }), "pm_restricted");
+        return check(timed(MSGPM_T_PM_RESTRICTED, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, fresh, s); }), "pm_restricted");
       },
       [&](hipStream_t s) {
-        return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, s); }), "pm_restricted");
+        return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, s, [&] { return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, fresh, s); }), "pm_restricted");
       });
 }
 
 // A pass of half-sweeps; a restricted pass reads the lists built before it.
+// The cost refresh that opens the pass (mode 0, or mode 1 for a restricted
+// one) is folded into the first half-sweep of each colour, which computes its
+// pixels' costs before their candidates; a pass without half-sweeps runs it
+// on its own.
 msgpm_status run_pm_pass(const Ctx& c, int slot, int restricted) {
+  if (c.P.iters == 0)
+    return check(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, restricted, c.s); }), "eval_cost");
   for (int it = 0; it < c.P.iters; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      msgpm_status st = run_halfsweep(c, colour, it, slot, restricted);
+      msgpm_status st = run_halfsweep(c, colour, it, slot, restricted, it == 0);
       if (st != MSGPM_OK) return st;
     }
   return MSGPM_OK;
@@ -362,8 +370,10 @@ msgpm_status msgpm_pm_halfsweep(const msgpm_params* p, void* d_ws, int colour, i
   if (st != MSGPM_OK) return st;
   if (colour != 0 && colour != 1) return fail(MSGPM_E_INVALID, "colour must be 0 or 1");
   if (iter < 0 || slot < 0 || slot > 255) return fail(MSGPM_E_INVALID, "iter or slot out of range");
-  if (restricted && (st = run_lists(c)) != MSGPM_OK) return st;
-  return run_halfsweep(c, colour, iter, slot, restricted ? 1 : 0);
+  if (restricted < 0 || restricted > (1 | MSGPM_PM_FRESH))
+    return fail(MSGPM_E_INVALID, "restricted must be 0 or 1, optionally with MSGPM_PM_FRESH");
+  if ((restricted & 1) && (st = run_lists(c)) != MSGPM_OK) return st;
+  return run_halfsweep(c, colour, iter, slot, restricted & 1, (restricted & MSGPM_PM_FRESH) ? 1 : 0);
 }
 
 msgpm_status msgpm_ransac(const msgpm_params* p, void* d_ws, int level, int stage, void* stream) {
@@ -446,7 +456,7 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
   RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb1, 0, c.s); }), "features");
   RUN(timed(MSGPM_T_FEATURES, c.s, [&] { return launch_features(c.P, c.w, d_rgb2, 1, c.s); }), "features");
   RUN(timed(MSGPM_T_INIT, c.s, [&] { return launch_init_state(c.P, c.w, d_init_nnf0, d_init_nnf1, c.s); }), "init_state");
-  RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 0, c.s); }), "eval_cost");
+  // the initial pass, its cost refresh folded into it
   if ((st = run_pm_pass(c, 0, 0)) != MSGPM_OK) return st;
   for (int l = 0; l < c.P.n_levels; ++l) {
     for (int stage = 1; stage <= 2; ++stage) {
@@ -458,9 +468,9 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
     RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_fb_unassign(c.P, c.w, c.s); }), "fb_unassign");
     if (c.P.cues & MSGPM_FLAG_CUE_UNIQUE) RUN(timed(MSGPM_T_FB, c.s, [&] { return launch_unique(c.P, c.w, c.s); }), "unique");
     RUN(timed(MSGPM_T_NNF_UPDATE, c.s, [&] { return launch_nnf_update(c.P, c.w, l, c.s); }), "nnf_update");
-    // the unassigned pixels' lists serve the cost refresh and the whole restricted pass
+    // the unassigned pixels' lists serve the whole restricted pass (its cost
+    // refresh folded into it)
     if ((st = run_lists(c)) != MSGPM_OK) return st;
-    RUN(timed(MSGPM_T_EVAL_COST, c.s, [&] { return launch_eval_cost(c.P, c.w, 1, c.s); }), "eval_cost");
     if ((st = run_pm_pass(c, l + 1, 1)) != MSGPM_OK) return st;
   }
   if (c.P.fill_sweeps > 0) RUN(timed(MSGPM_T_FILL, c.s, [&] { return launch_fill(c.P, c.w, c.s); }), "fill");
@@ -570,9 +580,11 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
   add(BK_FEATURES, MSGPM_T_FEATURES);
   add(BK_INIT_PIXELS, MSGPM_T_INIT);
   add(BK_INIT_PLANES, MSGPM_T_INIT);
-  add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 0);
+  // cost refreshes are folded into the first half-sweep of each colour (run
+  // alone when a pass has none)
+  if (P.iters == 0) add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 0);
   for (int it = 0; it < P.iters; ++it)
-    for (int colour = 0; colour < 2; ++colour) add(BK_PM_INIT, MSGPM_T_PM_INIT, colour, it, 0, 0);
+    for (int colour = 0; colour < 2; ++colour) add(BK_PM_INIT, MSGPM_T_PM_INIT, colour, it, 0, it == 0 ? 2 : 0);
   for (int l = 0; l < P.n_levels; ++l) {
     for (int stage = 1; stage <= 2; ++stage) {
       add(BK_RANSAC, MSGPM_T_RANSAC, l, stage);
@@ -587,12 +599,15 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
     add(BK_NNF_UPDATE, MSGPM_T_NNF_UPDATE, l);
     add(BK_ZERO_ACTIVE, MSGPM_T_PM_LIST);
     for (int colour = 0; colour < 2; ++colour) add(BK_ACTIVE_LIST, MSGPM_T_PM_LIST, colour);
-    add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 1);
-    add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
+    if (P.iters == 0) {
+      add(BK_EVAL_COST_IDENT, MSGPM_T_EVAL_COST, 1);
+      add(BK_EVAL_COST_PLANE, MSGPM_T_EVAL_COST, 1);
+    }
     for (int it = 0; it < P.iters; ++it)
       for (int colour = 0; colour < 2; ++colour) {
-        add(BK_PM_RESTRICTED, MSGPM_T_PM_RESTRICTED, colour, it, l + 1, 1);
-        add(BK_PM_RESTRICTED_IDENT, MSGPM_T_PM_RESTRICTED_IDENT, colour, it, l + 1, 1);
+        const int mode = it == 0 ? 3 : 1;
+        add(BK_PM_RESTRICTED, MSGPM_T_PM_RESTRICTED, colour, it, l + 1, mode);
+        add(BK_PM_RESTRICTED_IDENT, MSGPM_T_PM_RESTRICTED_IDENT, colour, it, l + 1, mode);
       }
   }
   if (P.fill_sweeps > 0) {

@@ -498,15 +498,22 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
 
 template <int R, int C, bool FP16>
 __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const DevParams& P, const Ws& w, int dir,
-                                           int x, int y, int base, const int* rox, const int* roy, unsigned& evals,
-                                           unsigned& rows) {
+                                           int x, int y, int base, bool fresh, const int* rox, const int* roy,
+                                           unsigned& evals, unsigned& rows) {
   constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G, NB = 4;
   const int W = P.W, H = P.H, p = y * W + x;
   const Feat F2 = feat_buf<C, FP16>(w.feat[1 - dir], W, H);
   const int32_t* nnf = w.nnf[dir];
   const int32_t v0 = nnf[p];
   int btx = x + off_dx(v0), bty = y + off_dy(v0);
-  float bc = w.cost[dir][p];
+  float bc;
+  if (fresh) {
+    bool rejected;
+    unsigned r0 = 0;
+    bc = group_cost<R, C, FP16, true, true, false>(L, F2, W, H, btx, bty, P.gw, base, 0.f, rejected, r0);
+  } else {
+    bc = w.cost[dir][p];
+  }
   const unsigned e0 = evals;
   {
     int tx[4], ty[4];
@@ -552,7 +559,7 @@ __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const D
 
 template <int R, int C, bool FP16, bool IDENT, bool INTEGRAL>
 __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const DevParams& P, const Ws& w, int dir, int x,
-                                     int y, int base, bool has_plane, int ptx, int pty, const int* rox,
+                                     int y, int base, bool fresh, bool has_plane, int ptx, int pty, const int* rox,
                                      const int* roy, unsigned& evals, unsigned& rows) {
   constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G;
   constexpr bool EE = true;
@@ -561,7 +568,14 @@ __device__ inline void pm_candidates_serial(const LaneCol<R, C, IDENT>& L, const
   const int32_t* nnf = w.nnf[dir];
   const int32_t v0 = nnf[p];
   int btx = x + off_dx(v0), bty = y + off_dy(v0);
-  float bc = w.cost[dir][p];
+  float bc;
+  if (fresh) {
+    bool rejected;
+    unsigned r0 = 0;
+    bc = group_cost<R, C, FP16, IDENT, INTEGRAL, false>(L, F2, W, H, btx, bty, P.gw, base, 0.f, rejected, r0);
+  } else {
+    bc = w.cost[dir][p];
+  }
   int cdx = 0, cdy = 0;
   for (int k = 0; k < 5 + P.nk; ++k) {
     int tx, ty;
@@ -703,10 +717,15 @@ __global__ __launch_bounds__(kBlock) void kb_active_list(const PairDesc* __restr
 // ---------------------------------------------------------------------------
 // The distorted-patch form is held to 168 VGPRs (3 waves per SIMD): on MI355X
 // the extra wave hides more gather latency than the few registers it costs.
+// mode bit 0: restricted; bit 1 (fresh): the pixel's current cost is computed
+// first, as the cost refresh of that pass computes it, instead of being read,
+// so that the first half-sweep of each colour stands in for the refresh.
 template <int R, int C, bool FP16, bool IDENT>
 __device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& w, Blk bk, int colour, int iter,
-                                                  int slot, int restricted) {
+                                                  int slot, int mode) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
+  const int restricted = mode & 1;
+  const bool fresh = (mode & 2) != 0;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int g = lane / G, j = lane - g * G, base = g * G;
   const int dir = bk.y;
@@ -734,7 +753,7 @@ __device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& 
     act = act && x < W;
   }
   const int p = y * W + x;
-  unsigned evals = 0, rows = 0;
+  unsigned evals = 0, rows = 0, refreshed = 0;
   if (act) {
     const int label = restricted ? w.hlabel[dir][p] : -1;
     const double* Hp = plane_H(w, label);
@@ -783,24 +802,28 @@ __device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& 
         }
       }
       if constexpr (IDENT)
-        pm_candidates_ident<R, C, FP16>(L, P, w, dir, x, y, base, rox, roy, evals, rows);
+        pm_candidates_ident<R, C, FP16>(L, P, w, dir, x, y, base, fresh, rox, roy, evals, rows);
       else if (geo == 1)
-        pm_candidates_serial<R, C, FP16, IDENT, true>(L, P, w, dir, x, y, base, has_plane, ptx, pty, rox, roy, evals,
-                                                      rows);
+        pm_candidates_serial<R, C, FP16, IDENT, true>(L, P, w, dir, x, y, base, fresh, has_plane, ptx, pty, rox, roy,
+                                                      evals, rows);
       else
-        pm_candidates_serial<R, C, FP16, IDENT, false>(L, P, w, dir, x, y, base, has_plane, ptx, pty, rox, roy,
-                                                       evals, rows);
+        pm_candidates_serial<R, C, FP16, IDENT, false>(L, P, w, dir, x, y, base, fresh, has_plane, ptx, pty, rox,
+                                                       roy, evals, rows);
+    } else if (fresh && j == 0) {
+      w.cost[dir][p] = __builtin_huge_valf();
     }
     if (j != 0) evals = rows = 0;
+    refreshed = fresh && j == 0 ? 1 : 0;
   }
   count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 10 : 4) : 0) + dir, evals);
   count_evals<IDENT>(w.counters, (restricted ? (IDENT ? 12 : 8) : 6) + dir, rows);
+  if (fresh) count_evals<IDENT>(w.counters, 2 + dir, refreshed);
 }
 
 template <int R, int C, bool FP16, bool IDENT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void k_pm_halfsweep(
-    DevParams P, Ws w, int colour, int iter, int slot, int restricted) {
-  pm_halfsweep_body<R, C, FP16, IDENT>(P, w, blk_here(), colour, iter, slot, restricted);
+    DevParams P, Ws w, int colour, int iter, int slot, int mode) {
+  pm_halfsweep_body<R, C, FP16, IDENT>(P, w, blk_here(), colour, iter, slot, mode);
 }
 
 template <int R, int C, bool FP16, bool IDENT>
@@ -817,26 +840,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
 // Launchers
 // ---------------------------------------------------------------------------
 template <int R, int C, bool FP16, bool IDENT>
-static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
+static hipError_t pm_launch(const DevParams& P, const Ws& w, int colour, int iter, int slot, int mode,
                             hipStream_t s) {
   constexpr int G = 2 * R + 1, NG = kWave / G;
   const long long n = (long long)((P.W + 1) >> 1) * P.H;
   const long long per = (long long)NG * (kBlock / kWave);
   const int nb = (int)((n + per - 1) / per);
   hipLaunchKernelGGL((k_pm_halfsweep<R, C, FP16, IDENT>), dim3(nb, 2), dim3(kBlock), 0, s, P, w, colour, iter, slot,
-                     restricted);
+                     mode);
   return hipGetLastError();
 }
 
-// Restricted half-sweep: list the pixels (launch_pm_list), then the
-// distorted-patch kernel over the front list and the identity-patch kernel over
-// the back one (both read only the other colour, so their order does not
-// matter).
+// Restricted half-sweep over the lists of launch_pm_lists: the distorted-patch
+// kernel over the front list or the identity-patch kernel over the back one
+// (both read only the other colour, so their order does not matter).
 template <int R, int C, bool FP16>
 static hipError_t dispatch_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
-                                      hipStream_t s) {
-  if (ident) return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 1, s);
-  return pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, 1, s);
+                                      int fresh, hipStream_t s) {
+  const int mode = 1 | (fresh ? 2 : 0);
+  if (ident) return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, mode, s);
+  return pm_launch<R, C, FP16, false>(P, w, colour, iter, slot, mode, s);
 }
 
 // The lists of both colours; they hold for every half-sweep of a restricted
@@ -864,10 +887,9 @@ static hipError_t ec_launch(const DevParams& P, const Ws& w, int mode, hipStream
 }
 
 template <int R, int C, bool FP16>
-static hipError_t dispatch_pm(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
+static hipError_t dispatch_pm(const DevParams& P, const Ws& w, int colour, int iter, int slot, int fresh,
                               hipStream_t s) {
-  (void)restricted;
-  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, 0, s);
+  return pm_launch<R, C, FP16, true>(P, w, colour, iter, slot, fresh ? 2 : 0, s);
 }
 
 template <int R, int C, bool FP16>
@@ -896,14 +918,14 @@ static hipError_t dispatch_ec(const DevParams& P, const Ws& w, int mode, hipStre
     }                                                                                 \
   } while (0)
 
-hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int restricted,
+hipError_t launch_pm_halfsweep(const DevParams& P, const Ws& w, int colour, int iter, int slot, int fresh,
                                hipStream_t s) {
-  MSGPM_DISPATCH(dispatch_pm, P, w, colour, iter, slot, restricted, s);
+  MSGPM_DISPATCH(dispatch_pm, P, w, colour, iter, slot, fresh, s);
 }
 
 hipError_t launch_pm_restricted(const DevParams& P, const Ws& w, int colour, int iter, int slot, int ident,
-                                hipStream_t s) {
-  MSGPM_DISPATCH(dispatch_restricted, P, w, colour, iter, slot, ident, s);
+                                int fresh, hipStream_t s) {
+  MSGPM_DISPATCH(dispatch_restricted, P, w, colour, iter, slot, ident, fresh, s);
 }
 
 hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream_t s) {

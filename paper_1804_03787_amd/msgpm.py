@@ -20,6 +20,7 @@ FLAG_FP16 = 1
 FLAG_CUE_OVERLAP = 2  # occlusion cue 3: plane kept only if its consistent pixels mostly match its RANSAC test
 FLAG_CUE_UNIQUE = 4   # occlusion cue 2: one assigned pixel per target
 FLAG_HISTEQ = 8       # equalise the frames' HSV value channel before the features
+PM_FRESH = 2          # pm_halfsweep: compute each swept pixel's current cost first (folds the cost refresh in)
 
 STATUS = {0: "OK", 1: "E_INVALID", 3: "E_DEVICE", 4: "E_UNSUPPORTED"}
 

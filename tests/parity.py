@@ -37,6 +37,27 @@ def push_state(o: oracle.Oracle, g: msgpm.Pair):
     torch.cuda.synchronize()
 
 
+def poison_refresh(o: oracle.Oracle, g: msgpm.Pair, colour: int, mode: int) -> int:
+    """After push_state: sets to zero, on the GPU, the costs that a cost refresh
+    of `mode` (0: every pixel, 1: the unassigned ones) sets on the pixels of
+    `colour`.  No candidate beats a zero cost, so a half-sweep that read them
+    would keep every offset: a sweep with PM_FRESH must compute them itself.
+    Returns the number of costs replaced."""
+    H, W = o.Hh, o.Ww
+    ys, xs = np.mgrid[0:H, 0:W]
+    n = 0
+    for d in range(2):
+        sel = ((xs + ys) % 2).ravel() == colour
+        if mode == 1:
+            sel &= o.win[d] < 0
+        c = o.cost[d].astype(np.float32)
+        c[sel] = 0.0
+        n += int(sel.sum())
+        g.cost(d).copy_(torch.from_numpy(c).to(g.device))
+    torch.cuda.synchronize()
+    return n
+
+
 def pull_state(g: msgpm.Pair) -> dict:
     torch.cuda.synchronize()
     s = {}

@@ -7,13 +7,16 @@ oracle's exact state and compared as in the small lock-step tests.
 The oracle needs about 25 s per PatchMatch half-sweep at this size, so these
 tests cover single steps of each kind rather than the whole pipeline:
   * features, the random initial NNF, the cost refresh and the first
-    half-sweep of the initial pass (identity patches, every pixel of a colour);
+    half-sweep of the initial pass (identity patches, every pixel of a colour),
+    then the first half-sweep of the other colour in the fused form the
+    pipeline runs (the refresh computed inside the sweep);
   * starting from an initial NNF made of the generator's ground-truth flow in
     both directions with 20 % of the offsets perturbed, every plane phase of
     the three levels (RANSAC stages 1 and 2, assignment, plane symmetry, FB,
-    NNF update), one restricted half-sweep after the first level (both the
-    distorted-patch kernel over pixels with a region plane and the
-    identity-patch kernel over those without), and the outputs; a third form
+    NNF update), one restricted half-sweep after the first level in the fused
+    form (the pass's cost refresh inside it; both the distorted-patch kernel
+    over pixels with a region plane and the identity-patch kernel over those
+    without), and the outputs; a third form
     (scene seed 2) adds occlusion cues 2 and 3 and the filling.
 """
 import ctypes
@@ -45,15 +48,37 @@ def _pair(seed):
 
 
 def _lockstep(o, g, steps, p):
+    """Runs the steps on both sides from the oracle's state, comparing after
+    each.  ("fresh", (colour, iter, slot, restricted)) is a half-sweep that
+    computes its pixels' costs itself, as the whole pipeline runs the first
+    half-sweep of each colour: the oracle runs the cost refresh (unless an
+    ("eval_cost", ...) step already did) and the plain half-sweep, the GPU the
+    fused sweep with those costs zeroed beforehand."""
+    from paper_1804_03787_amd import msgpm
     report = dict(pm_flagged=0, pm_flagged_diff=0, pm_unexplained=0, ransac_nonexact=0, steps=0)
+    refreshed = False
     for name, args in steps:
         for d in range(2):
             o.pflag[d][:] = 0
         o.bflag[:] = 0
-        parity.push_state(o, g)
-        o.run_step(name, args)
-        _gpu_step(g, name, args)
+        if name == "fresh":
+            colour, it, slot, restricted = args
+            if not refreshed:
+                o.run_step("eval_cost", (restricted,))
+            parity.push_state(o, g)
+            assert parity.poison_refresh(o, g, colour, restricted) > 0
+            o.run_step("pm_halfsweep", args)
+            g.pm_halfsweep(colour, it, slot, restricted | msgpm.PM_FRESH)
+            name = "pm_halfsweep"
+        else:
+            refreshed = name == "eval_cost"
+            parity.push_state(o, g)
+            o.run_step(name, args)
+            _gpu_step(g, name, args)
         got = parity.pull_state(g)
+        if name == "pm_halfsweep":
+            for d in range(2):
+                assert np.array_equal(np.isfinite(got["cost"][d]), np.isfinite(o.cost[d])), (name, args, d)
         _check_step(name, args, o, got, None, p, report)
         report["steps"] += 1
     return report
@@ -92,7 +117,9 @@ def test_full_size_initial_pass_step(form):
             print(f"FP16 storage, cost relative error against FP32 features, dir {d}: "
                   f"median {q[0]:.2e}, p99 {q[1]:.2e}, max {q[2]:.2e}")
             assert q[0] < 1e-3
-    report = _lockstep(o, g, [("pm_halfsweep", (0, 0, 0, 0))], p)
+    # the first half-sweep of colour 0 after the refresh, then that of colour 1
+    # with the refresh folded in, as the pipeline runs it
+    report = _lockstep(o, g, [("pm_halfsweep", (0, 0, 0, 0)), ("fresh", (1, 0, 0, 0))], p)
     assert report["pm_unexplained"] == 0
     print("full-size initial pass", form, report)
 
@@ -127,7 +154,8 @@ def test_full_size_plane_phases(form):
         steps += [("fb_unassign", ())] + ([("unique", ())] if p.get("cue_unique") else [])
         steps += [("nnf_update", (lv,))]
         if lv == 0:
-            steps += [("eval_cost", (1,)), ("pm_halfsweep", (0, 0, 1, 1))]
+            # the restricted pass's cost refresh folded into its first half-sweep
+            steps += [("fresh", (0, 0, 1, 1))]
     if p.get("fill_sweeps"):
         steps += [("fill", ())]
     report = _lockstep(o, g, steps, p)

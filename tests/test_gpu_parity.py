@@ -246,6 +246,56 @@ def test_lockstep_pipeline(case):
     print(case, report)
 
 
+@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "ragged", "paper_preset"])
+def test_lockstep_fresh_halfsweeps(case):
+    """The cost refresh folded into the first half-sweep of each colour
+    (PM_FRESH, as the whole pipeline runs it).  The GPU is fed the oracle's
+    state with the costs the refresh would set replaced by zeros (a cost no
+    candidate beats, so a sweep that read them would keep every offset); its
+    fused sweep must give what the oracle's refresh followed by its plain
+    half-sweep gives, to the bar of the plain half-sweep."""
+    msgpm = _need_gpu()
+    make, p = CASES[case]
+    pair = make()
+    H, W = pair.shape
+    o = oracle.Oracle(pair.frame1, pair.frame2, **p)
+    g = msgpm.Pair(W, H, **_gpu_params(p))
+    g.set_features(pair.frame1, pair.frame2)
+    g.init_state()
+    for d in range(2):
+        o.nnf_init(d)
+    report = dict(pm_flagged=0, pm_flagged_diff=0, pm_unexplained=0, ransac_nonexact=0, steps=0)
+    pending, fused, poisoned_total = {}, 0, 0
+    for name, args in o.schedule():
+        for d in range(2):
+            o.pflag[d][:] = 0
+        o.bflag[:] = 0
+        if name == "eval_cost":
+            o.run_step(name, args)  # the GPU folds it into the next two half-sweeps
+            pending = {0: args[0], 1: args[0]}
+            continue
+        parity.push_state(o, g)
+        if name == "pm_halfsweep" and args[0] in pending:
+            colour, it, slot, restricted = args
+            mode = pending.pop(colour)
+            assert it == 0 and restricted == mode
+            poisoned_total += parity.poison_refresh(o, g, colour, mode)
+            o.run_step(name, args)
+            g.pm_halfsweep(colour, it, slot, restricted | msgpm.PM_FRESH)
+            fused += 1
+            got = parity.pull_state(g)
+            for d in range(2):
+                assert np.array_equal(np.isfinite(got["cost"][d]), np.isfinite(o.cost[d])), (args, d)
+        else:
+            o.run_step(name, args)
+            _gpu_step(g, name, args)
+            got = parity.pull_state(g)
+        _check_step(name, args, o, got, None, p, report)
+        report["steps"] += 1
+    assert fused == 2 * (1 + len(p["blocks"])) and poisoned_total > 0
+    print(case, report, "fused sweeps", fused, "poisoned costs", poisoned_total)
+
+
 @pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill", "tiny_histeq"])
 def test_solve_end_to_end(case):
     """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
@@ -295,6 +345,8 @@ def test_invalid_arguments_raise():
         g.ransac(3, 1)
     with pytest.raises(msgpm.MsgpmError):
         g.pm_halfsweep(2, 0, 0, 0)
+    with pytest.raises(msgpm.MsgpmError):
+        g.pm_halfsweep(0, 0, 0, 4)
 
 
 def test_fp16_storage_precision_report():
