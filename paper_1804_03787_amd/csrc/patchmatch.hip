@@ -496,11 +496,38 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
   }
 }
 
+// Random-search candidates k0 .. k0 + NB - 1 around (x + cdx, y + cdy), as one
+// identity-patch batch.
+template <int R, int C, bool FP16, int NB>
+__device__ inline void random_batch(const LaneCol<R, C, true>& L, const DevParams& P, Feat F2, int x, int y,
+                                    int cdx, int cdy, int k0, int base, const int* rox, const int* roy, int& btx,
+                                    int& bty, float& bc, unsigned& evals) {
+  constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G;
+  const int W = P.W, H = P.H;
+  int tx[NB], ty[NB];
+  bool ok[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int kk = k0 + b;
+    const int src = base + (kk % G), slot_k = kk / G;
+    int mx = rox[0], my = roy[0];
+#pragma unroll
+    for (int h = 1; h < NH; ++h) {
+      mx = slot_k == h ? rox[h] : mx;
+      my = slot_k == h ? roy[h] : my;
+    }
+    tx[b] = clampi(x + cdx + __shfl(mx, src), 0, W - 1);
+    ty[b] = clampi(y + cdy + __shfl(my, src), 0, H - 1);
+    ok[b] = !(tx[b] == btx && ty[b] == bty);
+  }
+  ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
+}
+
 template <int R, int C, bool FP16>
 __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const DevParams& P, const Ws& w, int dir,
                                            int x, int y, int base, bool fresh, const int* rox, const int* roy,
                                            unsigned& evals, unsigned& rows) {
-  constexpr int G = 2 * R + 1, NH = (16 + G - 1) / G, NB = 4;
+  constexpr int G = 2 * R + 1, NB = 4;
   const int W = P.W, H = P.H, p = y * W + x;
   const Feat F2 = feat_buf<C, FP16>(w.feat[1 - dir], W, H);
   const int32_t* nnf = w.nnf[dir];
@@ -530,26 +557,19 @@ __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const D
     }
     ident_batch<R, C, FP16, 4>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
   }
+  // random search in full batches, then one batch of the remaining radii (a
+  // wave-uniform size, so no slot loads a patch for a radius that is not there)
   const int cdx = btx - x, cdy = bty - y;
-  for (int k0 = 0; k0 < P.nk; k0 += NB) {
-    int tx[NB], ty[NB];
-    bool ok[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int kk = k0 + b;
-      const int src = base + (kk % G), slot_k = kk / G;
-      int mx = rox[0], my = roy[0];
-#pragma unroll
-      for (int h = 1; h < NH; ++h) {
-        mx = slot_k == h ? rox[h] : mx;
-        my = slot_k == h ? roy[h] : my;
-      }
-      tx[b] = clampi(x + cdx + __shfl(mx, src), 0, W - 1);
-      ty[b] = clampi(y + cdy + __shfl(my, src), 0, H - 1);
-      ok[b] = kk < P.nk && !(tx[b] == btx && ty[b] == bty);
-    }
-    ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
-  }
+  int k0 = 0;
+  for (; k0 + NB <= P.nk; k0 += NB)
+    random_batch<R, C, FP16, NB>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+  const int rest = P.nk - k0;
+  if (rest == 3)
+    random_batch<R, C, FP16, 3>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+  else if (rest == 2)
+    random_batch<R, C, FP16, 2>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+  else if (rest == 1)
+    random_batch<R, C, FP16, 1>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
   rows += (evals - e0) * G;
   if (base == (int)(threadIdx.x & (kWave - 1))) {
     w.nnf[dir][p] = pack_off(btx - x, bty - y);
