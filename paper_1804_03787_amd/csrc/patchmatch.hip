@@ -523,6 +523,20 @@ __device__ inline void random_batch(const LaneCol<R, C, true>& L, const DevParam
   ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, ok, P.gw, base, btx, bty, bc, evals);
 }
 
+// The last random-search batch, of rest < NB candidates (rest is the same for
+// every lane).
+template <int R, int C, bool FP16, int N>
+__device__ inline void random_rest(int rest, const LaneCol<R, C, true>& L, const DevParams& P, Feat F2, int x, int y,
+                                   int cdx, int cdy, int k0, int base, const int* rox, const int* roy, int& btx,
+                                   int& bty, float& bc, unsigned& evals) {
+  if constexpr (N > 0) {
+    if (rest == N)
+      random_batch<R, C, FP16, N>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+    else
+      random_rest<R, C, FP16, N - 1>(rest, L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+  }
+}
+
 template <int R, int C, bool FP16>
 __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const DevParams& P, const Ws& w, int dir,
                                            int x, int y, int base, bool fresh, const int* rox, const int* roy,
@@ -563,13 +577,7 @@ __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const D
   int k0 = 0;
   for (; k0 + NB <= P.nk; k0 += NB)
     random_batch<R, C, FP16, NB>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
-  const int rest = P.nk - k0;
-  if (rest == 3)
-    random_batch<R, C, FP16, 3>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
-  else if (rest == 2)
-    random_batch<R, C, FP16, 2>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
-  else if (rest == 1)
-    random_batch<R, C, FP16, 1>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
+  random_rest<R, C, FP16, NB - 1>(P.nk - k0, L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals);
   rows += (evals - e0) * G;
   if (base == (int)(threadIdx.x & (kWave - 1))) {
     w.nnf[dir][p] = pack_off(btx - x, bty - y);
