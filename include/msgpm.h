@@ -377,7 +377,8 @@ msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
    each kept as 64 partial sums to be added by the reader), per direction
    d = 0, 1, reset by msgpm_init_state:
      [0 + d] candidates evaluated by the initial PatchMatch pass,
-     [2 + d] cost refreshes, [4 + d] candidates of the restricted passes at
+     [2 + d] cost refreshes (also those computed by MSGPM_PM_FRESH
+     half-sweeps), [4 + d] candidates of the restricted passes at
      pixels with a region plane, [10 + d] at pixels without one,
      [6 + d], [8 + d], [12 + d] patch rows (2r+1 taps each) actually computed
      by the initial pass and the two restricted kinds (a candidate rejected
