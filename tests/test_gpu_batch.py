@@ -83,6 +83,15 @@ def test_batch_with_cues_filling_and_equalisation_matches_single_solves():
     _run(msgpm, pairs, [dict(base), dict(base, seed=6, blocks=(20,))])
 
 
+def test_batch_without_sweeps_matches_single_solves():
+    """No PatchMatch iterations: the batch runs the passes' cost refreshes as
+    launches of their own, as the single solve does."""
+    msgpm = _need_gpu()
+    pairs = [synth.tiny_pair(0), synth.planar_pair(97, 61, seed=4, scale=0.1)]
+    base = _gpu_params(dict(TINY_PARAMS, iters=0))
+    _run(msgpm, pairs, [dict(base), dict(base, seed=6, blocks=(20,))])
+
+
 def test_batch_rejects_mixed_options():
     msgpm = _need_gpu()
     base = _gpu_params(TINY_PARAMS)

@@ -76,6 +76,10 @@ CASES = {
     # no plane levels at all: PatchMatch alone, every pixel occluded, an empty
     # plane table (and a filling with nothing to propagate)
     "no_levels": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, blocks=(), fill_sweeps=4)),
+    # no PatchMatch iterations: the passes are their cost refreshes alone (run on
+    # their own, not folded into a first half-sweep), the planes are fitted to
+    # the random initial NNF
+    "no_sweeps": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, iters=0)),
     # a frame smaller than the patch and the window (9x7, 9x9 patches, 8-pixel
     # windows): every gather clamps, one wave holds the whole frame
     "minimal": (lambda: _two_layer_pair(9, 7, 43),
@@ -296,7 +300,7 @@ def test_lockstep_fresh_halfsweeps(case):
     print(case, report, "fused sweeps", fused, "poisoned costs", poisoned_total)
 
 
-@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill", "tiny_histeq"])
+@pytest.mark.parametrize("case", ["tiny_c5", "tiny_c5_fp16", "tiny_cues", "tiny_fill", "tiny_histeq", "no_sweeps"])
 def test_solve_end_to_end(case):
     """Free-running whole pipeline: decisions cascade from PatchMatch near-ties,
     so the comparison is statistical: offsets, masks and flows of the GPU run
@@ -315,11 +319,15 @@ def test_solve_end_to_end(case):
         fg_ = fg[d].cpu().numpy()
         occ_agree = (og_ == oo[d]).mean()
         both = (og_ == 0) & (oo[d] == 0)
-        epe_delta = np.linalg.norm(fg_ - fo[d], axis=-1)[both].mean()
-        nnf_agree = (g.nnf(d).cpu().numpy() == o.nnf[d]).mean()
-        print(case, d, "occ agree", occ_agree, "nnf agree", nnf_agree, "EPE delta", epe_delta)
+        epe_delta = np.linalg.norm(fg_ - fo[d], axis=-1)[both].mean() if both.any() else 0.0
+        nnf_same = g.nnf(d).cpu().numpy() == o.nnf[d]
+        print(case, d, "occ agree", occ_agree, "nnf agree", nnf_same.mean(), "EPE delta", epe_delta,
+              "assigned", both.mean())
         assert occ_agree > 0.98
         assert epe_delta <= 0.01
+        # occluded on both sides with the same offset: the flow is that offset
+        none = ((og_ == 1) & (oo[d] == 1)).reshape(-1) & nnf_same
+        assert np.array_equal(fg_.reshape(-1, 2)[none], fo[d].reshape(-1, 2)[none])
 
 
 def test_solve_is_deterministic():
