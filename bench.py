@@ -47,8 +47,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 # pipeline run; None when not measured for the kernels as they are now.
 TRAFFIC = {
     # profiles/k_pm_halfsweep_1024x436_traffic.md
-    "k_pm_halfsweep (identity patches)": 1.579e9,
-    "k_pm_halfsweep (distorted patches)": 3.417e8,
+    "k_pm_halfsweep (identity patches)": 1.526e9,
+    "k_pm_halfsweep (distorted patches)": 3.411e8,
 }
 
 
