@@ -203,8 +203,8 @@ __device__ inline float tap_sq(const float* f1, const float* v, float gw) {
 // of the group.  Eight adds with the wave shifted right by one lane leave at
 // lane l the sum ((v[l-G+1] + v[l-G+2]) + ...) + v[l]; at the group's last lane
 // that is its G partials in lane order, which is then broadcast (by lane reads
-// for up to nine groups: measured on MI355X, 0.1 ms per pair faster than a
-// permute through LDS on the distorted-patch sweeps' chain of sums).  Groups never
+// for up to nine groups: measured on MI355X, faster than a permute through
+// LDS by 0.1 ms per pair with FP32 records and 1.6 ms with FP16 records).  Groups never
 // straddle inactive lanes: a group is active or inactive as a whole.
 template <int G>
 __device__ inline float group_sum(float v, int base) {
@@ -446,11 +446,13 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const PairDesc* __restric
 
 // Group costs of NB identity-patch targets: each lane walks its column once,
 // issuing the loads of all NB candidates per tap; every candidate is summed in
-// the same order as a lone evaluation.  The early rejection is decided per
-// wave (measured on MI355X: 1 % faster per pair; a second check at two thirds
-// of the rows adds spills and gains nothing measurable), since skipping rows
-// of single candidates takes branches inside the load chunk that make the
-// compiler spill.
+// the same order as a lone evaluation.  With FP32 records the early rejection
+// is decided per wave (measured on MI355X: 1 % faster per pair; a second check
+// at two thirds of the rows adds spills and gains nothing measurable), since
+// skipping rows of single candidates takes branches inside the load chunk that
+// make the compiler spill.  FP16 records need half the load instructions and
+// there the extra partial sums cost more than the rows they save (8 % slower
+// per pair), so those batches are always summed to the end.
 // Tap rows per load chunk of identity-patch batches: one (measured on MI355X, two
 // or three rows per chunk take the kernel to 256 VGPRs and lose more than the
 // longer chunks gain).
@@ -486,8 +488,8 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
   }
 }
 
-// After the first third of the rows, if no candidate the batch evaluates, in
-// any group of the wave, has a partial sum below `bound` (the best cost when
+// FP32 records: after the first third of the rows, if no candidate the batch
+// evaluates, in any group of the wave, has a partial sum below `bound` (the best cost when
 // the batch starts), none can be strictly better: taps are non-negative and
 // FP32 addition is monotone, so the full sums are at least the partial ones.
 // The wave then skips the other rows (returns false; costs are not set).
@@ -502,10 +504,12 @@ __device__ inline bool group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.f;
   ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
-  bool live = false;
+  if constexpr (!FP16) {
+    bool live = false;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) live = live || (ok[b] && group_sum<T>(acc[b], base) < bound);
-  if (__ballot(live) == 0ull) return false;
+    for (int b = 0; b < NB; ++b) live = live || (ok[b] && group_sum<T>(acc[b], base) < bound);
+    if (__ballot(live) == 0ull) return false;
+  }
   ident_rows<R, C, FP16, NB, TE, T>(acc, L, F2, W, H, tx, ty, gw);
 #pragma unroll
   for (int b = 0; b < NB; ++b) cost[b] = group_sum<T>(acc[b], base);
