@@ -76,6 +76,10 @@ CASES = {
     # no plane levels at all: PatchMatch alone, every pixel occluded, an empty
     # plane table (and a filling with nothing to propagate)
     "no_levels": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, blocks=(), fill_sweeps=4)),
+    # random-search start radii of 16 and 32: 5 and 6 radii, so the last
+    # identity-patch batch holds 1 and 2 candidates (the other cases leave 0 or 3)
+    "tiny_r0_16": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, R0=16)),
+    "tiny_r0_32": (lambda: synth.tiny_pair(0), dict(TINY_PARAMS, R0=32)),
     # no PatchMatch iterations: the passes are their cost refreshes alone (run on
     # their own, not folded into a first half-sweep), the planes are fitted to
     # the random initial NNF
