@@ -444,23 +444,14 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const PairDesc* __restric
 //  * distorted patches (long chain, register-heavy): one candidate at a time
 //    with the exact early rejection of group_cost.
 
-// Group costs of NB identity-patch targets: each lane walks its column once,
-// issuing the loads of all NB candidates per tap; every candidate is summed in
-// the same order as a lone evaluation.  With FP32 records the early rejection
-// is decided per wave (measured on MI355X: 1 % faster per pair; a second check
-// at two thirds of the rows adds spills and gains nothing measurable), since
-// skipping rows of single candidates takes branches inside the load chunk that
-// make the compiler spill.  FP16 records need half the load instructions and
-// there the extra partial sums cost more than the rows they save (8 % slower
-// per pair), so those batches are always summed to the end.
 // Tap rows per load chunk of identity-patch batches: one (measured on MI355X, two
 // or three rows per chunk take the kernel to 256 VGPRs and lose more than the
 // longer chunks gain).
 constexpr int kIdentRows = 1;
 
-// Rows [T0, T1) of NB identity-patch targets added to acc, in chunks of
-// kIdentRows: the loads of a chunk (all candidates) are issued ahead of its
-// arithmetic.
+// Rows [T0, T) of NB identity-patch targets added to acc, in chunks of
+// kIdentRows: each lane walks its column once, and the loads of a chunk (all
+// candidates) are issued ahead of its arithmetic.
 template <int R, int C, bool FP16, int NB, int T0, int T>
 __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                   const int* ty, float gw) {
@@ -488,13 +479,19 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
   }
 }
 
-// FP32 records: after the first third of the rows, if no candidate the batch
-// evaluates, in any group of the wave, has a partial sum below `bound` (the best cost when
-// the batch starts), none can be strictly better: taps are non-negative and
-// FP32 addition is monotone, so the full sums are at least the partial ones.
-// The wave then skips the other rows (returns false; costs are not set).
-// Otherwise every candidate is summed to the end, in the same order as a lone
-// evaluation.
+// Group costs of NB identity-patch targets, every candidate summed in the same
+// order as a lone evaluation.  FP32 records: after the first third of the
+// rows, if no candidate the batch evaluates, in any group of the wave, has a
+// partial sum below `bound` (the best cost when the batch starts), none can be
+// strictly better: taps are non-negative and FP32 addition is monotone, so the
+// full sums are at least the partial ones.  The wave then skips the other rows
+// (returns false; costs are not set).  The decision is taken per wave because
+// skipping rows of single candidates takes branches inside the load chunk that
+// make the compiler spill (measured on MI355X: 1 % faster per pair; a second
+// check at two thirds of the rows adds spills and gains nothing measurable).
+// FP16 records need half the load instructions, and there the extra partial
+// sums cost more than the rows they save (8 % slower per pair), so those
+// batches are always summed to the end.
 template <int R, int C, bool FP16, int NB>
 __device__ inline bool group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                               const int* ty, const bool* ok, float bound, float gw, int base,
