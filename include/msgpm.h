@@ -67,6 +67,18 @@ typedef enum msgpm_status {
    R, G, B are scaled by V'/V (V <= 0: grey V'); a frame whose pixels all share
    one level is used as it is.  The frames themselves are not modified. */
 #define MSGPM_FLAG_HISTEQ 8u
+/* Merge flag: the level priority of Sec. 3.3 (when the levels' flows are
+   merged, earlier levels, whose windows are larger and so less disturbed by
+   noisy matches, come first) taken strictly.  A pixel assigned at some level
+   keeps that plane: the assignment of every later level (both stages) is
+   offered only the pixels that are unassigned when it runs, as stage 2 always
+   is (Sec. 3.2).  RANSAC, the plane-symmetry counts and the forward-backward
+   checks are unchanged (the end-of-level check can still unassign a pixel,
+   which a later level may then assign).  Without the flag every stage-1
+   assignment is offered every pixel, and a finer level's plane replaces the
+   incumbent when its loss is strictly smaller, the level breaking exact ties
+   in favour of the coarser one (key (L, level, stage, window)). */
+#define MSGPM_FLAG_MERGE_STRICT 16u
 
 /* Method parameters.  Defaults in brackets are those of the 1024x436 workload. */
 typedef struct msgpm_params {

@@ -14,39 +14,61 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "msgpm_oracle.c")
+HDR = os.path.join(_HERE, "msgpm_oracle.h")
 LIB = os.path.join(_HERE, "libmsgpm_oracle.so")
+LIB_OMP = os.path.join(_HERE, "libmsgpm_oracle_omp.so")
+# Single-threaded build: the parity authority.  An OpenMP build of the same
+# source (LIB_OMP) shares the phase loops among threads and gives the same
+# bits.  MSGPM_ORACLE_LIB names another single-threaded build to load instead
+# (the mutation test points it at deliberately broken copies).
+_LIB_ENV = "MSGPM_ORACLE_LIB"
 
 PI_FIELDS = ["dir", "level", "stage", "block", "x0", "y0", "bw", "bh", "support", "count", "hyp",
              "hyp_count", "refit", "detected", "rk", "pass", "valid", "rin"]
 PI = {n: i for i, n in enumerate(PI_FIELDS)}
 
-F_COST, F_ROUND, F_COLOUR, F_FB, F_BOUNDS, F_RANSAC = 1, 2, 4, 8, 16, 32
+F_COST, F_ROUND, F_COLOUR, F_FB, F_BOUNDS, F_RANSAC, F_TWOBEST = 1, 2, 4, 8, 16, 32, 64
 B_RCOUNT, B_SYMCOUNT = 64, 128
 
 DEFAULTS = dict(C=5, r=4, grad_weight=1.0, blocks=(64, 32, 16), iters=8, hyps=256, R0=0, tau=1.0, eps=0.1,
                 tau_fb=1.0, mu=0.25, m_min_abs=8, eta=(1, 2), seed=0, fp16=False, cue_overlap=False,
-                cue_unique=False, fill_sweeps=0, histeq=False)
+                cue_unique=False, fill_sweeps=0, histeq=False, merge_strict=False)
 CUE_OVERLAP, CUE_UNIQUE = 1, 2
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", LIB, SRC,
-           "-lm"]
+def compile_oracle(src: str, out: str, openmp: bool = False, extra=(), verbose: bool = False) -> str:
+    """Compiles one oracle source file into a shared library."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-Wno-unknown-pragmas", "-fPIC",
+           "-shared", *(["-fopenmp"] if openmp else []), *extra, "-I", _HERE, "-o", out, src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    compile_oracle(SRC, LIB, verbose=verbose)
+    compile_oracle(SRC, LIB_OMP, openmp=True, verbose=verbose)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = ctypes.CDLL(LIB)
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(SRC), os.path.getmtime(HDR))
+
+
+def lib(variant: str = "serial"):
+    """The oracle library: "serial" (the parity authority) or "omp"."""
+    if variant not in _libs:
+        if variant == "serial" and os.environ.get(_LIB_ENV):
+            path = os.environ[_LIB_ENV]
+        else:
+            path = LIB if variant == "serial" else LIB_OMP
+            if _stale(path):
+                compile_oracle(SRC, path, openmp=(variant == "omp"))
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER(_Pair)
         vp = ctypes.c_void_p
         i = ctypes.c_int
@@ -82,13 +104,19 @@ def lib():
             "orc_nnf_update": (None, [P, i, i]),
             "orc_finalize": (None, [P, i, vp, vp]),
             "orc_solve": (None, [P, vp, vp, vp, vp, vp, vp]),
+            "orc_set_threads": (i, [i]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
+
+
+def set_threads(n: int) -> int:
+    """Threads of the OpenMP build's phase loops; returns the count in use."""
+    return int(lib("omp").orc_set_threads(n))
 
 
 class _Pair(ctypes.Structure):
@@ -106,6 +134,7 @@ class _Pair(ctypes.Structure):
         ("tloss", ctypes.c_void_p * 2), ("pflag", ctypes.c_void_p * 2),
         ("P", ctypes.c_int32), ("pH", ctypes.c_void_p), ("pinfo", ctypes.c_void_p), ("bflag", ctypes.c_void_p),
         ("evals", ctypes.c_int64), ("cues", ctypes.c_int32), ("fill_sweeps", ctypes.c_int32),
+        ("merge_strict", ctypes.c_int32),
     ]
 
 
@@ -188,11 +217,13 @@ def unpack(v):
 class Oracle:
     """One frame pair with its full per-direction state, driven phase by phase
     or end to end.  Arrays are numpy and may be read or overwritten between
-    phases (to feed identical state to another implementation)."""
+    phases (to feed identical state to another implementation).  variant
+    "omp" runs the phases on the OpenMP build (same results, see lib())."""
 
-    def __init__(self, frame1: np.ndarray, frame2: np.ndarray, **params):
+    def __init__(self, frame1: np.ndarray, frame2: np.ndarray, variant: str = "serial", **params):
         p = dict(DEFAULTS)
         p.update(params)
+        self._L = lib(variant)
         self.params = p
         self.Hh, self.Ww = frame1.shape[:2]
         H, W = self.Hh, self.Ww
@@ -224,15 +255,16 @@ class Oracle:
         s.seed = p["seed"]
         s.cues = (CUE_OVERLAP if p["cue_overlap"] else 0) | (CUE_UNIQUE if p["cue_unique"] else 0)
         s.fill_sweeps = p["fill_sweeps"]
+        s.merge_strict = int(bool(p["merge_strict"]))
         self.s = s
         self._bind()
-        P = lib().orc_plane_capacity(ctypes.byref(s))
+        P = self._L.orc_plane_capacity(ctypes.byref(s))
         s.P = P
         self.pH = np.zeros((P, 9), np.float64)
         self.pinfo = np.zeros((P, len(PI_FIELDS)), np.int32)
         self.bflag = np.zeros(P, np.uint8)
         s.pH, s.pinfo, s.bflag = _ptr(self.pH), _ptr(self.pinfo), _ptr(self.bflag)
-        lib().orc_planes_init(ctypes.byref(s))
+        self._L.orc_planes_init(ctypes.byref(s))
 
     def _bind(self):
         s = self.s
@@ -258,33 +290,33 @@ class Oracle:
 
     # -- helpers ---------------------------------------------------------
     def plane_index(self, d, level, stage, block):
-        return lib().orc_plane_index(self.ref, d, level, stage, block)
+        return self._L.orc_plane_index(self.ref, d, level, stage, block)
 
     def block_grid(self, level):
         B = self.params["blocks"][level]
-        return lib().orc_block_count(self.Ww, B), lib().orc_block_count(self.Hh, B)
+        return self._L.orc_block_count(self.Ww, B), self._L.orc_block_count(self.Hh, B)
 
     def m_min(self, bw, bh):
-        return lib().orc_m_min(self.ref, bw, bh)
+        return self._L.orc_m_min(self.ref, bw, bh)
 
     def cost_at(self, d, px, py, tx, ty, Hm=None):
         h = None if Hm is None else _ptr(np.ascontiguousarray(Hm, dtype=np.float64).reshape(9))
-        return lib().orc_cost(self.ref, d, px, py, tx, ty, h)
+        return self._L.orc_cost(self.ref, d, px, py, tx, ty, h)
 
     def cost_all(self, d):
         n = self.Ww * self.Hh
         out = np.zeros(n * n)
-        lib().orc_cost_all(self.ref, d, _ptr(out))
+        self._L.orc_cost_all(self.ref, d, _ptr(out))
         return out.reshape(n, n)
 
     def colour_err(self, d, px, py, Hm):
         h = np.ascontiguousarray(Hm, dtype=np.float64).reshape(9)
         nb = ctypes.c_int(0)
-        return lib().orc_colour_err(self.ref, d, px, py, _ptr(h), ctypes.byref(nb))
+        return self._L.orc_colour_err(self.ref, d, px, py, _ptr(h), ctypes.byref(nb))
 
     # -- phases ----------------------------------------------------------
     def nnf_init(self, d):
-        lib().orc_nnf_init(self.ref, d)
+        self._L.orc_nnf_init(self.ref, d)
 
     def set_nnf(self, d, nnf):
         """Install a caller-supplied NNF, clamping targets into the frame."""
@@ -297,10 +329,10 @@ class Oracle:
         self.nnf[d][:] = pack(tx - x, ty - y)
 
     def eval_cost(self, d, mode):
-        lib().orc_eval_cost(self.ref, d, mode)
+        self._L.orc_eval_cost(self.ref, d, mode)
 
     def pm_halfsweep(self, d, colour, it, slot, restricted):
-        lib().orc_pm_halfsweep(self.ref, d, colour, it, slot, restricted)
+        self._L.orc_pm_halfsweep(self.ref, d, colour, it, slot, restricted)
 
     def pm_pass(self, slot, restricted):
         for it in range(self.params["iters"]):
@@ -309,31 +341,31 @@ class Oracle:
                     self.pm_halfsweep(d, colour, it, slot, restricted)
 
     def ransac(self, d, level, stage):
-        lib().orc_ransac(self.ref, d, level, stage)
+        self._L.orc_ransac(self.ref, d, level, stage)
 
     def assign(self, d, level, stage, tentative):
-        lib().orc_assign(self.ref, d, level, stage, int(tentative))
+        self._L.orc_assign(self.ref, d, level, stage, int(tentative))
 
     def symmetry(self, level, stage):
-        lib().orc_symmetry(self.ref, level, stage)
+        self._L.orc_symmetry(self.ref, level, stage)
 
     def fb_unassign(self):
-        lib().orc_fb_unassign(self.ref)
+        self._L.orc_fb_unassign(self.ref)
 
     def unique(self):
-        lib().orc_unique(self.ref)
+        self._L.orc_unique(self.ref)
 
     def fill(self):
-        lib().orc_fill(self.ref)
+        self._L.orc_fill(self.ref)
 
     def nnf_update(self, d, level):
-        lib().orc_nnf_update(self.ref, d, level)
+        self._L.orc_nnf_update(self.ref, d, level)
 
     def finalize(self, d):
         W, H = self.Ww, self.Hh
         flow = np.zeros((H, W, 2), np.float32)
         occ = np.zeros((H, W), np.uint8)
-        lib().orc_finalize(self.ref, d, _ptr(flow), _ptr(occ))
+        self._L.orc_finalize(self.ref, d, _ptr(flow), _ptr(occ))
         return flow, occ
 
     def reset_state(self):
@@ -342,7 +374,7 @@ class Oracle:
             self.loss[d][:] = np.inf
             self.hlabel[d][:] = -1
             self.pflag[d][:] = 0
-        lib().orc_planes_init(self.ref)
+        self._L.orc_planes_init(self.ref)
 
     def solve(self, init_nnf=(None, None)):
         W, H = self.Ww, self.Hh
@@ -351,7 +383,7 @@ class Oracle:
         inits = []
         for a in init_nnf:
             inits.append(None if a is None else np.ascontiguousarray(a, dtype=np.int32).reshape(-1))
-        lib().orc_solve(self.ref, None if inits[0] is None else _ptr(inits[0]),
+        self._L.orc_solve(self.ref, None if inits[0] is None else _ptr(inits[0]),
                         None if inits[1] is None else _ptr(inits[1]), _ptr(flows[0]), _ptr(flows[1]),
                         _ptr(occs[0]), _ptr(occs[1]))
         return flows, occs

@@ -25,8 +25,21 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define TIE_REL 1e-9
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 static int imin(int a, int b) { return a < b ? a : b; }
@@ -335,6 +348,8 @@ static const double* region_H(const orc_pair* S, int label) { return label >= 0 
 
 void orc_eval_cost(orc_pair* S, int dir, int mode) {
   const int W = S->W, H = S->H;
+  int64_t evals = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evals)
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       int p = y * W + x;
@@ -349,8 +364,9 @@ void orc_eval_cost(orc_pair* S, int dir, int mode) {
       }
       int32_t v = S->nnf[dir][p];
       S->cost[dir][p] = orc_cost(S, dir, x, y, x + unpack_dx(v), y + unpack_dy(v), Hm);
-      S->evals++;
+      evals++;
     }
+  S->evals += evals;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -370,21 +386,27 @@ static int near_half(double q) {
   return fabs(f - 0.5) <= TIE_REL;
 }
 
+/* Running state of one pixel's update: the best target and its cost, the
+   second-best cost over distinct targets, near-tie flags, evaluations. */
 typedef struct {
   int tx, ty;
-  double c;
+  double c, c2;
   int flag;
+  int64_t evals;
 } pm_best;
 
-static void pm_try(orc_pair* S, int dir, int px, int py, int tx, int ty, const double* Hm, pm_best* b) {
+static void pm_try(const orc_pair* S, int dir, int px, int py, int tx, int ty, const double* Hm, pm_best* b) {
   if (tx == b->tx && ty == b->ty) return; /* same target: same cost, never strictly better */
   double c = orc_cost(S, dir, px, py, tx, ty, Hm);
-  S->evals++;
+  b->evals++;
   if (near_cost(S, c, b->c)) b->flag |= ORC_F_COST;
   if (c < b->c) {
+    b->c2 = b->c;
     b->tx = tx;
     b->ty = ty;
     b->c = c;
+  } else if (c < b->c2) {
+    b->c2 = c;
   }
 }
 
@@ -392,6 +414,10 @@ void orc_pm_halfsweep(orc_pair* S, int dir, int colour, int iter, int slot, int 
   const int W = S->W, H = S->H;
   const int R0 = S->R0 > 0 ? S->R0 : (W > H ? W : H);
   int32_t* nnf = S->nnf[dir];
+  int64_t evals = 0;
+  /* a pixel of this colour reads only the other colour's offsets and writes
+     only its own state, so the rows may be taken in any order */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : evals)
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       if (((x + y) & 1) != colour) continue;
@@ -403,7 +429,9 @@ void orc_pm_halfsweep(orc_pair* S, int dir, int colour, int iter, int slot, int 
       b.tx = x + unpack_dx(nnf[p]);
       b.ty = y + unpack_dy(nnf[p]);
       b.c = S->cost[dir][p];
+      b.c2 = INFINITY;
       b.flag = 0;
+      b.evals = 0;
       /* propagation from the four in-image neighbours: left, right, up, down */
       const int nx[4] = {x - 1, x + 1, x, x};
       const int ny[4] = {y, y, y - 1, y + 1};
@@ -436,8 +464,11 @@ void orc_pm_halfsweep(orc_pair* S, int dir, int colour, int iter, int slot, int 
       }
       nnf[p] = pack_off(b.tx - x, b.ty - y);
       S->cost[dir][p] = b.c;
+      if (near_cost(S, b.c, b.c2)) b.flag |= ORC_F_TWOBEST;
       if (S->pflag[dir]) S->pflag[dir][p] |= (uint8_t)b.flag;
+      evals += b.evals;
     }
+  S->evals += evals;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -604,6 +635,10 @@ void orc_ransac(orc_pair* S, int dir, int level, int stage) {
   const int nbx = orc_block_count(W, B), nby = orc_block_count(H, B);
   const int bw = imin(B, W), bh = imin(B, H);
   const double tau2 = S->tau * S->tau;
+  /* every window reads the NNF and assignment and writes only its own plane
+     record, so the windows may be fitted in any order */
+#pragma omp parallel
+  {
   int* px = (int*)malloc(sizeof(int) * (size_t)bw * bh * 4);
   int* py = px + bw * bh;
   int* qx = py + bw * bh;
@@ -614,9 +649,9 @@ void orc_ransac(orc_pair* S, int dir, int level, int stage) {
   double* aqy = aqx + bw * bh;
   int* cnt = (int*)malloc(sizeof(int) * (size_t)S->hyps * 2);
   int* nties = cnt + S->hyps;
-  for (int by = 0; by < nby; ++by)
-    for (int bx = 0; bx < nbx; ++bx) {
-      const int b = by * nbx + bx;
+#pragma omp for schedule(dynamic, 1)
+  for (int b = 0; b < nbx * nby; ++b) {
+    {
       const int k = orc_plane_index(S, dir, level, stage, b);
       int32_t* I = S->pinfo + (size_t)k * ORC_PI_N;
       double* Hk = S->pH + (size_t)k * 9;
@@ -748,9 +783,11 @@ void orc_ransac(orc_pair* S, int dir, int level, int stage) {
         if ((fragile & 2) || final_ties > 0) S->bflag[k] |= 64;
       }
     }
+  }
   free(px);
   free(ax);
   free(cnt);
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -819,6 +856,8 @@ void orc_assign(orc_pair* S, int dir, int level, int stage, int tentative) {
   const double eps2 = S->eps * S->eps;
   int32_t* out_win = tentative ? S->twin[dir] : S->win[dir];
   double* out_loss = tentative ? S->tloss[dir] : S->loss[dir];
+  /* a pixel reads and writes only its own assignment */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int y = 0; y < H; ++y) {
     int ylo, yhi;
     cover_range(H, B, y, &ylo, &yhi);
@@ -826,7 +865,10 @@ void orc_assign(orc_pair* S, int dir, int level, int stage, int tentative) {
       const int p = y * W + x;
       int bw_ = S->win[dir][p];
       double bl = S->loss[dir][p];
-      const int candidate = (stage == 1) || (bw_ < 0);
+      /* stage 2 takes only the residual (unassigned) pixels (Sec. 3.2); with the
+         strict level priority so does every stage of every level: a pixel keeps
+         the plane of the first level that assigned it (Sec. 3.3) */
+      const int candidate = (stage == 1 && !S->merge_strict) || (bw_ < 0);
       int flag = 0;
       if (candidate) {
         int xlo, xhi;
@@ -912,8 +954,12 @@ void orc_symmetry(orc_pair* S, int level, int stage) {
   const int B = S->block[level];
   const int nb = orc_block_count(W, B) * orc_block_count(H, B);
   const double eps2 = S->eps * S->eps;
-  for (int dir = 0; dir < 2; ++dir)
-    for (int b = 0; b < nb; ++b) {
+  /* a window writes only its own plane record and reads the other direction's
+     tentative assignment, which this step does not change */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int db = 0; db < 2 * nb; ++db) {
+    const int dir = db / nb, b = db % nb;
+    {
       const int k = orc_plane_index(S, dir, level, stage, b);
       int32_t* I = S->pinfo + (size_t)k * ORC_PI_N;
       I[ORC_PI_RK] = 0;
@@ -968,6 +1014,7 @@ void orc_symmetry(orc_pair* S, int level, int stage) {
             }
       }
     }
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -976,7 +1023,9 @@ void orc_symmetry(orc_pair* S, int level, int stage) {
 /* ------------------------------------------------------------------------ */
 void orc_fb_unassign(orc_pair* S) {
   const int n = S->W * S->H;
+  /* judged on the snapshot in win; the results go to twin first */
   for (int dir = 0; dir < 2; ++dir)
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < n; ++p) {
       int j = S->win[dir][p];
       S->twin[dir][p] = j;
@@ -1060,6 +1109,7 @@ void orc_fill(orc_pair* S) {
     int quiet = 0;
     for (int t = 0; t < S->fill_sweeps && quiet < 2; ++t) {
       int filled = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : filled)
       for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
           const int p = y * W + x;
@@ -1095,6 +1145,8 @@ void orc_nnf_update(orc_pair* S, int dir, int level) {
   const int W = S->W, H = S->H;
   const int B = S->block[level];
   const int nbx = orc_block_count(W, B);
+  /* a pixel writes only its own offset and label */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int y = 0; y < H; ++y) {
     int ylo, yhi;
     cover_range(H, B, y, &ylo, &yhi);
@@ -1134,6 +1186,7 @@ void orc_nnf_update(orc_pair* S, int dir, int level) {
 void orc_finalize(orc_pair* S, int dir, float* flow, uint8_t* occ) {
   const int W = S->W, H = S->H;
   orc_eval_cost(S, dir, 2);
+#pragma omp parallel for schedule(static)
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       const int p = y * W + x;

@@ -9,8 +9,14 @@
  * library; both follow the same written definitions (the paper plus the readings
  * listed in the design notes), each in its own code.
  *
- * Plain, slow, single-threaded C; every floating-point step is FP64 (features are
- * FP32 or FP16 values widened to FP64).  Built with -O2 -ffp-contract=off.
+ * Plain, slow C; every floating-point step is FP64 (features are FP32 or FP16
+ * values widened to FP64).  Built with -O2 -ffp-contract=off, single-threaded
+ * (the parity authority) and, from the same source, with -fopenmp: the loops
+ * over the pixels of a phase and over the windows of a level are then shared
+ * among threads.  Each such loop writes only its own element's state and reads
+ * only state no iteration of the loop writes, and every floating-point value
+ * is computed by one thread in the written order, so both builds give the same
+ * bits (asserted by a test).
  *
  * Every phase function also reports per-element near-tie flags: a bit is set when
  * a discrete decision taken for that element (an argmin, a threshold test, a
@@ -57,7 +63,10 @@ enum {
   ORC_F_COLOUR = 4,   /* colour-consistency threshold or plane-loss argmin */
   ORC_F_FB = 8,       /* forward-backward distance threshold */
   ORC_F_BOUNDS = 16,  /* image-bounds test */
-  ORC_F_RANSAC = 32   /* RANSAC hypothesis choice / inlier count */
+  ORC_F_RANSAC = 32,  /* RANSAC hypothesis choice / inlier count */
+  ORC_F_TWOBEST = 64  /* PatchMatch: the two best costs over distinct targets of one update are
+                         within the PatchMatch cost band (a narrower test than ORC_F_COST, which
+                         compares every candidate with the running best) */
 };
 
 typedef struct orc_pair {
@@ -92,6 +101,10 @@ typedef struct orc_pair {
   /* filling by homography-model propagation (Sec. 3.4.1): red-black
      half-sweeps, 0 = no filling */
   int32_t fill_sweeps;
+  /* level priority of Sec. 3.3 taken strictly: an assigned pixel is no
+     candidate of a later level (only unassigned pixels are assigned there);
+     0 = the lexicographic key (L, level, stage, block) over every pixel */
+  int32_t merge_strict;
 } orc_pair;
 
 enum {
@@ -102,6 +115,12 @@ enum {
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Threads of the phase loops when the library is built with OpenMP (the
+   result does not depend on it: every parallel loop writes disjoint elements
+   and reads nothing written in the same loop); returns the count in use, 1 in
+   the plain build. */
+int orc_set_threads(int n);
 
 /* Counter-based RNG: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

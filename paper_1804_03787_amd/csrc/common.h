@@ -23,6 +23,7 @@ struct DevParams {
   int cues;                          // MSGPM_FLAG_CUE_* bits
   int fill_sweeps;                   // half-sweeps of the filling, 0 = none
   int histeq;                        // equalise the frames' HSV value channel
+  int merge_strict;                  // strict level priority: only unassigned pixels are candidates
   int n_levels;
   int block[MSGPM_MAX_LEVELS];
   int nbx[MSGPM_MAX_LEVELS], nby[MSGPM_MAX_LEVELS];

@@ -23,6 +23,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local bool g_capturing = false;  // launches are being captured into a graph: no timing events
+thread_local bool g_no_events = false;  // a call that must not create HIP objects: no timing events
 
 msgpm_status fail(msgpm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 msgpm_status fail(msgpm_status s, const char* fmt, ...) {
@@ -73,7 +74,7 @@ Timer g_timer;
 
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
-  if (!g_timer.on || g_capturing) return launch();
+  if (!g_timer.on || g_capturing || g_no_events) return launch();
   std::lock_guard<std::mutex> lk(g_timer.mu);
   hipEvent_t a = g_timer.get(), b = g_timer.get();
   if (!a || !b) return hipErrorOutOfMemory;
@@ -105,7 +106,8 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   if (!(p->inlier_px > 0) || !(p->eps_color > 0) || !(p->fb_px > 0) || !(p->min_support_frac >= 0) ||
       !(p->grad_weight >= 0))
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
-  if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE | MSGPM_FLAG_HISTEQ))
+  if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE | MSGPM_FLAG_HISTEQ |
+                   MSGPM_FLAG_MERGE_STRICT))
     return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->fill_sweeps < 0 || p->fill_sweeps > 65536) return fail(MSGPM_E_INVALID, "fill_sweeps outside 0..65536");
   {
@@ -133,6 +135,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
   d.cues = (int)(p->flags & (MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE));
   d.fill_sweeps = p->fill_sweeps;
   d.histeq = (p->flags & MSGPM_FLAG_HISTEQ) ? 1 : 0;
+  d.merge_strict = (p->flags & MSGPM_FLAG_MERGE_STRICT) ? 1 : 0;
   d.n_levels = p->n_levels;
   int off = 0;
   for (int l = 0; l < p->n_levels; ++l) {
@@ -224,6 +227,7 @@ struct Ctx {
   msgpm_layout L;
   Ws w;
   hipStream_t s;
+  bool one_stream = false;  // restricted half-sweeps: both launches on s, one after the other
 };
 
 msgpm_status open_ctx(const msgpm_params* p, void* ws, void* stream, Ctx* c) {
@@ -293,6 +297,13 @@ msgpm_status run_lists(const Ctx& c) {
 msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restricted, int fresh) {
   if (!restricted)
     return check(timed(MSGPM_T_PM_INIT, c.s, [&] { return launch_pm_halfsweep(c.P, c.w, colour, it, slot, fresh, c.s); }), "pm_halfsweep");
+  if (c.one_stream) {
+    // the two launches update disjoint pixels and read only the other colour:
+    // in sequence they give the same result as side by side
+    msgpm_status st = check(launch_pm_restricted(c.P, c.w, colour, it, slot, 0, fresh, c.s), "pm_restricted");
+    if (st != MSGPM_OK) return st;
+    return check(launch_pm_restricted(c.P, c.w, colour, it, slot, 1, fresh, c.s), "pm_restricted");
+  }
   // distorted patches on the caller's stream, identity patches on the second one
   return side_by_side(
       c.s,

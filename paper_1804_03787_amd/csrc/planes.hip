@@ -872,7 +872,9 @@ __device__ __forceinline__ void assign_body(const DevParams& P, const Ws& w, Blk
   const int x = p % W, y = p / W;
   int bwin = w.win[dir][p];
   double bl = w.loss[dir][p];
-  if (stage == 1 || bwin < 0) {
+  // stage 2 offers only the residual pixels (Sec. 3.2); with the strict level
+  // priority (Sec. 3.3) every stage does: an assigned pixel keeps its plane
+  if ((stage == 1 && !P.merge_strict) || bwin < 0) {
     const int B = P.block[level], nbx = P.nbx[level], nby = P.nby[level];
     int xlo, xhi, ylo, yhi;
     cover_range(W, B, nbx, x, xlo, xhi);

@@ -23,6 +23,14 @@ if ROOT not in sys.path:
 
 W, H = 56, 40
 PARAMS = dict(C=5, r=2, blocks=(16,), iters=3, hyps=32, tau=1.0, eps=0.1, tau_fb=1.0, seed=9)
+# one level; two levels (windows 24 and 12, so the second level's merge, its
+# restricted pass and the label carried over from the first all take part),
+# with the default merge key and with the strict level priority
+CASES = {
+    "one_level": PARAMS,
+    "two_levels": dict(PARAMS, blocks=(24, 12)),
+    "two_levels_strict": dict(PARAMS, blocks=(24, 12), merge_strict=True),
+}
 
 
 def _texture(rng, h, w, k=5):
@@ -47,9 +55,13 @@ def frames():
 
 
 def summary():
+    return {name: case_summary(p) for name, p in CASES.items()}
+
+
+def case_summary(params):
     import oracle
     f1, f2 = frames()
-    o = oracle.Oracle(f1, f2, **PARAMS)
+    o = oracle.Oracle(f1, f2, **params)
     flows, occs = o.solve()
     digest = lambda a: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
     valid = o.pinfo[:, oracle.PI["valid"]]
@@ -60,7 +72,7 @@ def summary():
         "planes_sha256": digest(o.pH) + ":" + digest(o.pinfo),
         "occluded": [int(occs[d].sum()) for d in range(2)],
         "valid_planes": int(valid.sum()),
-        "params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in PARAMS.items()},
+        "params": {k: (list(v) if isinstance(v, tuple) else v) for k, v in params.items()},
         "size": [W, H],
     }
 

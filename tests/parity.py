@@ -86,3 +86,38 @@ def compare_planes(o: oracle.Oracle, gp: np.ndarray, sel=None, exact=True):
     if m.any():
         bad.append(f"H: {int(m.sum())} differ, first at {int(np.nonzero(m)[0][0])}")
     return bad
+
+
+# Near-tie flags of the oracle that excuse a different decision at a pixel:
+# PatchMatch cost comparisons, rounding, colour threshold or loss argmin,
+# forward-backward distance, image bounds.  TWO_BEST is the narrower PatchMatch
+# rule (the two best costs over distinct targets within the band) in place of
+# the running-best comparison.
+PIXEL_FLAGS = oracle.F_COST | oracle.F_ROUND | oracle.F_COLOUR | oracle.F_FB | oracle.F_BOUNDS
+TWO_BEST_FLAGS = oracle.F_TWOBEST | oracle.F_ROUND | oracle.F_COLOUR | oracle.F_FB | oracle.F_BOUNDS
+
+
+def free_run_compare(nnf_o, occ_o, flow_o, pflag_o, nnf_g, occ_g, flow_g) -> dict:
+    """One direction of a free-running solve against the oracle's.  Counts the
+    pixels whose NNF offset or mask differ, how many of them the oracle flags
+    as near-ties (under either rule), and the mean flow difference over the
+    pixels assigned on both sides (EPE delta)."""
+    nnf_o, nnf_g = nnf_o.reshape(-1), nnf_g.reshape(-1)
+    occ_o, occ_g = occ_o.reshape(-1), occ_g.reshape(-1)
+    pf = pflag_o.reshape(-1)
+    flag_any = (pf & PIXEL_FLAGS) != 0
+    flag_two = (pf & TWO_BEST_FLAGS) != 0
+    nd = nnf_o != nnf_g
+    od = occ_o != occ_g
+    both = (occ_o == 0) & (occ_g == 0)
+    fo, fg = flow_o.reshape(-1, 2), flow_g.reshape(-1, 2)
+    epe = float(np.linalg.norm(fg[both] - fo[both], axis=-1).mean()) if both.any() else 0.0
+    return {
+        "pixels": int(nnf_o.size),
+        "flagged": int(flag_any.sum()), "flagged_two_best": int(flag_two.sum()),
+        "nnf_differ": int(nd.sum()), "nnf_unexplained": int((nd & ~flag_any).sum()),
+        "nnf_unexplained_two_best": int((nd & ~flag_two).sum()),
+        "occ_differ": int(od.sum()), "occ_unexplained": int((od & ~flag_any).sum()),
+        "occ_unexplained_two_best": int((od & ~flag_two).sum()),
+        "assigned_both": int(both.sum()), "epe_delta": epe,
+    }

@@ -57,6 +57,10 @@ def test_layout_query_rejects_unknown_flags():
     p = msgpm.make_params(64, 48)
     p.flags = 1 << 7
     assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) != 0
+    p.flags = msgpm.FLAG_MERGE_STRICT
+    assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) == 0
+    p.flags = 1 << 5
+    assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) != 0
     assert b"flags" in msgpm.lib().msgpm_last_error()
 
 
@@ -100,8 +104,9 @@ def test_server_scratch_bytes():
 
 
 def test_oracle_matches_its_regression_anchor():
-    """The oracle's whole solve on the exactly reproducible small input equals the
-    stored fixture (tests/golden/make_oracle_golden.py wrote it from oracle/)."""
+    """The oracle's whole solves on the exactly reproducible small input (one
+    level; two levels with the default and the strict merge) equal the stored
+    fixture (tests/golden/make_oracle_golden.py wrote it from oracle/)."""
     import importlib.util
     spec = importlib.util.spec_from_file_location("make_oracle_golden",
                                                   os.path.join(ROOT, "tests", "golden", "make_oracle_golden.py"))
@@ -109,5 +114,7 @@ def test_oracle_matches_its_regression_anchor():
     spec.loader.exec_module(mod)
     want = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_small_solve.json")))
     got = json.loads(json.dumps(mod.summary()))
-    assert got["frames_sha256"] == want["frames_sha256"]
-    assert got == want
+    assert set(got) == set(want) == {"one_level", "two_levels", "two_levels_strict"}
+    for case in want:
+        assert got[case]["frames_sha256"] == want[case]["frames_sha256"]
+        assert got[case] == want[case], case
