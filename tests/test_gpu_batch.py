@@ -1,7 +1,8 @@
 """Batched solves (msgpm_solve_batch): pairs of uneven sizes share one launch
 per phase, and each pair's outputs (flow, occlusion, plane table, NNF) are
 bit-identical to a msgpm_solve of that pair alone.  GPU against GPU: the
-single-pair path is held to the oracle by the parity tests."""
+single-pair path is held to the oracle by the parity tests, and one batch of
+FP16-storage pairs is also compared with the oracle directly."""
 import numpy as np
 import pytest
 import torch
@@ -99,3 +100,31 @@ def test_batch_rejects_mixed_options():
         gs = [msgpm.Pair(128, 96, **base), msgpm.Pair(128, 96, **other)]
         with pytest.raises(msgpm.MsgpmError):
             msgpm.Batch(gs)
+
+
+def _against_oracle(pr, p, g, flows, occs):
+    """A pair's free-running result against the oracle's whole solve of it: NNF
+    and masks bit-exact outside flagged near-ties, EPE delta <= 0.01 px."""
+    import oracle
+    from tests import parity
+    o = oracle.Oracle(pr.frame1, pr.frame2, variant="omp", **p)
+    fo, oo = o.solve()
+    torch.cuda.synchronize()
+    for d in range(2):
+        rep = parity.free_run_compare(o.nnf[d], oo[d], fo[d], o.pflag[d], g.nnf(d).cpu().numpy(),
+                                      occs[d].cpu().numpy(), flows[d].cpu().numpy())
+        print(d, rep)
+        assert rep["nnf_unexplained"] == 0 and rep["occ_unexplained"] == 0 and rep["epe_delta"] <= 0.01, rep
+
+
+def test_batch_fp16_pairs_against_oracle():
+    """The batched FP16-storage form against the FP64 oracle directly (on the
+    same FP16-rounded features): a 128x96 pair and a 160x120 pair of another
+    scene, batched together."""
+    msgpm = _need_gpu()
+    scenes = [(synth.tiny_pair(0), dict(TINY_PARAMS, fp16=True)),
+              (synth.planar_pair(160, 120, seed=3, scale=0.15), dict(TINY_PARAMS, fp16=True, seed=5))]
+    gs = [msgpm.Pair(pr.shape[1], pr.shape[0], **_gpu_params(p)) for pr, p in scenes]
+    res = msgpm.Batch(gs).solve([pr.frame1 for pr, _ in scenes], [pr.frame2 for pr, _ in scenes])
+    for (pr, p), g, (flows, occs) in zip(scenes, gs, res):
+        _against_oracle(pr, p, g, flows, occs)

@@ -1,7 +1,8 @@
 """Serving (msgpm_server_*): pairs submitted while others are in flight are
 admitted within an HBM budget and co-batched step by step with pairs at other
 steps; each pair's outputs are bit-identical to a msgpm_solve of that pair
-alone (GPU against GPU)."""
+alone (GPU against GPU); one served FP16-storage mix is also compared with
+the oracle directly."""
 import numpy as np
 import pytest
 import torch
@@ -127,3 +128,31 @@ def test_serving_cancel_queued_and_in_flight():
     g, flows, occs = srv.result(t)
     _same(alone[2], _outputs(g, flows, occs))
     srv.close()
+
+
+def test_served_fp16_pairs_against_oracle():
+    """Pairs served with continuous batching (FP16 storage, the second
+    submitted while the first is in flight) against the FP64 oracle directly."""
+    from tests.test_gpu_batch import _against_oracle
+    msgpm = _need_gpu()
+    scenes = [(synth.tiny_pair(0), dict(TINY_PARAMS, fp16=True)),
+              (synth.planar_pair(160, 120, seed=3, scale=0.15), dict(TINY_PARAMS, fp16=True, seed=5))]
+    srv = msgpm.Server(hbm_budget=1 << 34, max_active=4)
+    tickets, done = {}, {}
+    rnd = 0
+    while len(done) < len(scenes):
+        if rnd in (0, 7):
+            k = 0 if rnd == 0 else 1
+            pr, p = scenes[k]
+            tickets[srv.submit(msgpm.Pair(pr.shape[1], pr.shape[0], **_gpu_params(p)), pr.frame1, pr.frame2)] = k
+        srv.step()
+        for t, k in list(tickets.items()):
+            if srv.poll(t):
+                done[k] = srv.result(t)
+                del tickets[t]
+        rnd += 1
+        assert rnd < 100000
+    srv.close()
+    for k, (pr, p) in enumerate(scenes):
+        g, flows, occs = done[k]
+        _against_oracle(pr, p, g, flows, occs)
