@@ -295,6 +295,29 @@ msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const
                                float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, void* stream);
 msgpm_status msgpm_graph_cache_clear(void);
 
+/* msgpm_solve without any allocation, for callers that cannot allocate device
+ * memory or create HIP objects (code under stream capture, tight serving
+ * loops, harnesses that forbid it).  The workspace is not an argument: it is
+ * a static array of MSGPM_STATIC_WS_BYTES inside the library's device code,
+ * one per GPU, held from the library's first use on that GPU until the
+ * process ends (64 MiB: enough for 1024x436 frames with 5 FP32 channels,
+ * whose workspace is 58.8 MB).  Parameters whose msgpm_layout_query
+ * total_bytes exceeds it are rejected with MSGPM_E_INVALID and nothing is
+ * enqueued.  Frames, initial NNF and outputs are as for msgpm_solve; d_planes
+ * (may be NULL) receives the plane table, layout.n_planes records, by a
+ * device-to-device copy.  Everything runs on `stream`, in order (the two
+ * launches of a restricted half-sweep one after the other, with the results
+ * of msgpm_solve bit for bit); no stream, event, graph or memory is created
+ * and kernel timing does not see these launches.  All calls on one GPU share
+ * its array, and the array keeps the last call's state: calls that overlap on
+ * one GPU (two streams, two threads) race and corrupt each other, so callers
+ * must order them. */
+#define MSGPM_STATIC_WS_BYTES (64ull << 20)
+msgpm_status msgpm_solve_static(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                                const int32_t* d_init_nnf0, const int32_t* d_init_nnf1, float* d_flow0,
+                                float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1, msgpm_plane* d_planes,
+                                void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched solves: the pipeline of msgpm_solve for n frame pairs at once, one
  * launch per phase covering every pair (pairs of different sizes share the

@@ -569,6 +569,75 @@ msgpm_status msgpm_graph_cache_clear(void) {
 
 }  // extern "C"
 
+// ---- the whole pipeline without allocation ---------------------------------
+// The workspace of msgpm_solve_static: one array per device, part of the
+// library's device code object, so it exists on every GPU the library runs on
+// until the process ends.  Host code never uses its name as an address: the
+// array's device address is read once per device (hipGetSymbolAddress, with
+// that device current) and kept in g_scratch_ptr.
+static_assert(MSGPM_STATIC_WS_BYTES % 256 == 0, "static workspace size");
+static __device__ __align__(256) unsigned char scratch[MSGPM_STATIC_WS_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // per device, nullptr until looked up
+
+// Device address of the current device's copy of `scratch`.
+msgpm_status scratch_address(void** out) {
+  int dev = -1;
+  msgpm_status st = check(hipGetDevice(&dev), "current device");
+  if (st != MSGPM_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(MSGPM_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    st = check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static workspace address");
+    if (st != MSGPM_OK) return st;
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255))
+      return fail(MSGPM_E_DEVICE, "static workspace address %p not 256-byte aligned", ptr);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MSGPM_OK;
+}
+
+struct NoEvents {
+  NoEvents() { g_no_events = true; }
+  ~NoEvents() { g_no_events = false; }
+};
+}  // namespace
+
+extern "C" msgpm_status msgpm_solve_static(const msgpm_params* p, const float* d_rgb1, const float* d_rgb2,
+                                           const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
+                                           float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1,
+                                           msgpm_plane* d_planes, void* stream) {
+  Ctx c;
+  msgpm_status st = prepare(p, &c.P, &c.L);
+  if (st != MSGPM_OK) return st;
+  if (c.L.total_bytes > MSGPM_STATIC_WS_BYTES)
+    return fail(MSGPM_E_INVALID, "workspace of %llu bytes for %dx%d exceeds the static workspace of %llu bytes",
+                (unsigned long long)c.L.total_bytes, p->width, p->height, (unsigned long long)MSGPM_STATIC_WS_BYTES);
+  if (!d_rgb1 || !d_rgb2 || !d_flow0 || !d_flow1 || !d_occ0 || !d_occ1)
+    return fail(MSGPM_E_INVALID, "frame or output pointer is NULL");
+  void* base = nullptr;
+  if ((st = scratch_address(&base)) != MSGPM_OK) return st;
+  c.w = make_ws(c.P, c.L, base);
+  c.s = static_cast<hipStream_t>(stream);
+  c.one_stream = true;  // no second stream: nothing is created
+  NoEvents quiet;       // no timing events either
+  // every array the pipeline reads is written by it first (features with their
+  // pad pixel, initial state, plane records, counters, lists), so what earlier
+  // calls left in the array does not matter
+  if ((st = solve_sequence(c, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_flow0, d_flow1, d_occ0, d_occ1)) !=
+      MSGPM_OK)
+    return st;
+  if (!d_planes) return MSGPM_OK;
+  return check(hipMemcpyAsync(d_planes, static_cast<char*>(base) + c.L.planes,
+                              (size_t)c.L.n_planes * sizeof(msgpm_plane), hipMemcpyDeviceToDevice, c.s),
+               "plane table copy");
+}
+
 namespace {
 
 // ---- batched solves ----------------------------------------------------------

@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_fill": [P, vp, vp],
             "msgpm_nnf_update": [P, vp, i, vp],
             "msgpm_finalize": [P, vp, vp, vp, vp, vp, vp],
+            "msgpm_solve_static": [P, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -319,6 +320,20 @@ class Pair:
               _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _stream())
         self._keep = (a, b, i0, i1)
         return flows, occs
+
+
+STATIC_WS_BYTES = 64 << 20  # MSGPM_STATIC_WS_BYTES
+
+
+def solve_static(p: Params, rgb1, rgb2, flows, occs, planes=None, init0=None, init1=None):
+    """msgpm_solve_static: the whole pipeline in the library's static workspace
+    (no allocation, no stream or event created).  rgb1, rgb2: device HWC
+    float32 frames; flows, occs: device outputs as for Pair.solve; planes:
+    optional device uint8 tensor of n_planes * 144 bytes for the plane table;
+    init0/init1: optional device int32 initial NNFs.  Every argument is a
+    caller-owned device tensor; nothing is allocated here."""
+    _call("msgpm_solve_static", ctypes.byref(p), _ptr(rgb1), _ptr(rgb2), _ptr(init0), _ptr(init1),
+          _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _ptr(planes), _stream())
 
 
 def solve(frame1, frame2, **params):
