@@ -15,12 +15,13 @@ hypotheses per window, FP32 patch costs, FP64 plane fits.
 Prints one JSON line: flow Mpix/s of the timed steps (each step one launch of
 the pipeline captured as a HIP graph, msgpm_solve_graph; --no-graph: eager
 launches), the dominant kernel's roofline (from an equal number of eager steps
-timed with HIP events around each launch) and the FP64 CPU oracle timed on a
-bounded sample on this host.
+timed with HIP events around each launch) and the FP64 CPU oracle (its OpenMP
+build, all of this host's cores) timed on the same 1024x436 pair.
 
 Other workloads: --fp16 (FP16 feature storage), --cues (occlusion cues 2 and
 3 on), --fill N (N half-sweeps of filling by model propagation), --histeq
-(HSV value equalisation of the frames), --seed,
+(HSV value equalisation of the frames), --strict (strict level priority),
+--independent (every quad moving on its own by up to 100 px), --seed,
 --batched (uneven
 pairs per msgpm_solve_batch), --serving (Poisson arrivals, continuous
 batching).
@@ -64,25 +65,40 @@ def flops_per_eval(kind: str, r: int, C: int) -> int:
     return taps * (12 * C + extra)
 
 
-def cpu_baseline(cues: bool = False, fill: int = 0, histeq: bool = False) -> dict:
-    """The FP64 oracle (single-threaded C) over the whole pipeline on a
-    128x56 instance of the same scene generator (lengths scaled by 1/8), same
-    method parameters and a first random-search radius of 1024 as in the full
-    workload."""
-    import numpy as np  # noqa: F401
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(cues: bool = False, fill: int = 0, histeq: bool = False, full: bool = True,
+                 seed: int = 0, fp16: bool = False, strict: bool = False, independent: bool = False) -> dict:
+    """The FP64 oracle over the whole pipeline, both directions, in its OpenMP
+    build (the phase loops shared among all the host's cores; the same bits as
+    the single-threaded build).  full: the 1024x436 pair itself (about 30 s
+    with 16 threads); otherwise a 512x218 instance of the 1024x436 scene
+    generator (lengths x1/2) with the same method parameters and a first
+    random-search radius of 1024, as in the full workload, so that a pixel does
+    the same work."""
     import oracle
     from paper_1804_03787_amd import synth
-    sw, sh = 128, 56
-    pair = synth.planar_pair(sw, sh, seed=0, scale=0.125)
-    o = oracle.Oracle(pair.frame1, pair.frame2, R0=1024,
-                      **dict(PARAMS, cue_overlap=cues, cue_unique=cues, fill_sweeps=fill, histeq=histeq))
+    sw, sh = (W, H) if full else (W // 2, H // 2)
+    pair = synth.planar_pair(sw, sh, seed=seed, scale=sw / W, independent=independent)
+    cores = oracle.set_threads(os.cpu_count() or 1)
+    o = oracle.Oracle(pair.frame1, pair.frame2, variant="omp", R0=max(W, H),
+                      **dict(PARAMS, cue_overlap=cues, cue_unique=cues, fill_sweeps=fill, histeq=histeq, fp16=fp16,
+                             merge_strict=strict))
     t0 = time.perf_counter()
     o.solve()
     dt = time.perf_counter() - t0
-    return {"value": round(sw * sh / dt / 1e6, 6), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole pipeline, both directions, on a {sw}x{sh} instance of the 1024x436 scene "
-                      f"generator (lengths x1/8), same parameters, R0=1024; {dt:.1f} s"}
+    what = "the 1024x436 pair itself" if full else f"a {sw}x{sh} instance of the 1024x436 scene generator (lengths x1/2)"
+    return {"value": round(sw * sh / dt / 1e6, 6), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole pipeline, both directions, on {what}, same parameters, R0=1024; {dt:.1f} s with "
+                      f"{cores} threads (OpenMP build of the FP64 oracle) on {_cpu_model()}"}
 
 
 BATCH_SIZES = [(320, 240), (640, 360), (1024, 436), (1280, 544)]
@@ -333,6 +349,11 @@ def main() -> int:
     ap.add_argument("--cues", action="store_true", help="occlusion cues 2 (uniqueness) and 3 (overlap) on")
     ap.add_argument("--fill", type=int, default=0, help="half-sweeps of filling by model propagation (0 = none)")
     ap.add_argument("--histeq", action="store_true", help="equalise the frames' HSV value channel first")
+    ap.add_argument("--strict", action="store_true", help="strict level priority (MSGPM_FLAG_MERGE_STRICT)")
+    ap.add_argument("--independent", action="store_true",
+                    help="scene with every quad moving on its own (up to 100 px, scale 0.9-1.1, 10 degrees)")
+    ap.add_argument("--cpu-sample", action="store_true",
+                    help="time the CPU oracle on a 512x218 instance instead of the 1024x436 pair itself")
     ap.add_argument("--batched", action="store_true",
                     help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
     ap.add_argument("--pairs", type=int, default=48)
@@ -355,11 +376,11 @@ def main() -> int:
     from paper_1804_03787_amd import msgpm, synth
 
     msgpm.lib()  # fails loudly if the HIP library is missing
-    pair = synth.planar_pair(W, H, seed=args.seed)
+    pair = synth.planar_pair(W, H, seed=args.seed, independent=args.independent)
     f1 = torch.from_numpy(pair.frame1).cuda()
     f2 = torch.from_numpy(pair.frame2).cuda()
     params = dict(PARAMS, fp16=args.fp16, cue_overlap=args.cues, cue_unique=args.cues, fill_sweeps=args.fill,
-                  histeq=args.histeq)
+                  histeq=args.histeq, merge_strict=args.strict)
     g = msgpm.Pair(W, H, **params)
     flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
     occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
@@ -450,7 +471,8 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.cues, args.fill, args.histeq)
+        cpu = cpu_baseline(args.cues, args.fill, args.histeq, full=not args.cpu_sample, seed=args.seed, fp16=args.fp16,
+                           strict=args.strict, independent=args.independent)
 
     line = {
         "metric": "flow Mpix/s (full pipeline)",
@@ -468,7 +490,8 @@ def main() -> int:
         "config": {"workload": "piecewise-planar pair 1024x436, fwd+bwd, patch 9x9, C=5, windows 64/32/16, "
                                "8 PM iterations, 256 RANSAC hypotheses",
                    "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16),
-                   "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill, "histeq": bool(args.histeq)},
+                   "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill, "histeq": bool(args.histeq),
+                   "merge_strict": bool(args.strict), "independent_quads": bool(args.independent)},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
         # the initial pass alone: its evaluations over its kernel time, beside the

@@ -41,9 +41,14 @@ extern "C" {
 
 typedef enum msgpm_status {
   MSGPM_OK = 0,
-  MSGPM_E_INVALID = 1,     /* bad argument: sizes, parameters, null pointer */
-  MSGPM_E_DEVICE = 3,      /* the HIP runtime reported an error */
-  MSGPM_E_UNSUPPORTED = 4  /* valid but not built (e.g. patch radius > 4) */
+  MSGPM_E_INVALID = 1,     /* bad argument: sizes, parameters, null pointer, unknown ticket */
+  MSGPM_E_OOM = 2,         /* memory: a request that can never fit a server's budget, or an
+                              allocation the library makes (pinned staging, events) failed */
+  MSGPM_E_DEVICE = 3,      /* the HIP runtime reported an error (also: no device) */
+  MSGPM_E_UNSUPPORTED = 4, /* valid but not built (e.g. patch radius > 4) */
+  MSGPM_E_BUSY = 5,        /* transient refusal: a server's queue is full; retry later */
+  MSGPM_E_CANCELLED = 6,   /* the pair was cancelled (msgpm_server_wait) */
+  MSGPM_E_TIMEOUT = 7      /* the pair was not done within the timeout (msgpm_server_wait) */
 } msgpm_status;
 
 /* Storage flag: features stored as binary16 (FP16) with FP32 accumulation. */
@@ -364,13 +369,28 @@ typedef struct msgpm_server msgpm_server;
 msgpm_status msgpm_server_create(uint64_t hbm_budget, int max_active, msgpm_server** out);
 msgpm_status msgpm_server_destroy(msgpm_server* server);
 msgpm_status msgpm_server_scratch_bytes(int max_active, uint64_t* bytes);
+/* Queues a pair.  MSGPM_E_OOM: its workspace (layout.total_bytes) exceeds
+   hbm_budget, so it could never be admitted.  MSGPM_E_BUSY: the queue already
+   holds the limit set by msgpm_server_set_queue_limit (a transient refusal:
+   submit again once pairs have been admitted).  Nothing is queued on an error. */
 msgpm_status msgpm_server_submit(msgpm_server* server, const msgpm_params* p, const float* d_rgb1,
                                  const float* d_rgb2, const int32_t* d_init_nnf0, const int32_t* d_init_nnf1,
                                  void* d_ws, float* d_flow0, float* d_flow1, uint8_t* d_occ0, uint8_t* d_occ1,
                                  uint64_t* ticket);
+/* Largest number of pairs waiting for admission (0 = no limit, the default). */
+msgpm_status msgpm_server_set_queue_limit(msgpm_server* server, int max_queued);
 /* *pending: pairs queued or still being launched after this round. */
 msgpm_status msgpm_server_step(msgpm_server* server, void* d_scratch, void* stream, int* pending);
 msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done);
+/* Waits until the pair's work has completed on the device, then retires the
+   ticket as msgpm_server_poll does: MSGPM_OK when its results are complete,
+   MSGPM_E_CANCELLED when it was cancelled in flight (its outputs are then
+   undefined).  MSGPM_E_TIMEOUT after timeout_us microseconds (0: check once;
+   negative: no limit) if it is not done; the ticket then stays valid.  A pair
+   is done only after the msgpm_server_step calls that launch its last step,
+   so a caller that waits with no limit must step the server from another
+   thread.  Unknown ticket: MSGPM_E_INVALID. */
+msgpm_status msgpm_server_wait(msgpm_server* server, uint64_t ticket, int64_t timeout_us);
 /* Cancels a pair.  Queued: removed at once, its ticket retired (*retired = 1,
    may be NULL).  In flight: it takes part in no further round; the next
    msgpm_server_step marks the end of the work already enqueued for it, after
@@ -378,6 +398,12 @@ msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done)
    its budget is released; its buffers may be written until then.  Fully
    launched: no effect, the pair completes normally. */
 msgpm_status msgpm_server_cancel(msgpm_server* server, uint64_t ticket, int* retired);
+
+/* Test hook for the failure paths: the next n allocations the library itself
+   makes (pinned host staging buffers, HIP events of the batched and serving
+   forms) fail as if out of memory, and the call that needed one returns
+   MSGPM_E_OOM with nothing enqueued.  0 switches the injection off. */
+msgpm_status msgpm_debug_fail_allocations(int n);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing.  While enabled, the library records a pair of HIP events on

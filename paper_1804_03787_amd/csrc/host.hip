@@ -5,11 +5,16 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
 #include <deque>
 #include <map>
+#include <thread>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "common.h"
 
@@ -38,7 +43,28 @@ msgpm_status fail(msgpm_status s, const char* fmt, ...) {
 
 msgpm_status check(hipError_t e, const char* what) {
   if (e == hipSuccess) return MSGPM_OK;
-  return fail(MSGPM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? MSGPM_E_OOM : MSGPM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Allocations the library makes itself (pinned staging, events of the batched
+// and serving forms) go through these two, so that a test can make them fail.
+std::atomic<int> g_fail_allocs{0};
+
+bool injected_failure() {
+  int n = g_fail_allocs.load();
+  while (n > 0)
+    if (g_fail_allocs.compare_exchange_weak(n, n - 1)) return true;
+  return false;
+}
+
+hipError_t host_alloc(void** p, size_t bytes) {
+  if (injected_failure()) return hipErrorOutOfMemory;
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+hipError_t event_create(hipEvent_t* e) {
+  if (injected_failure()) return hipErrorOutOfMemory;
+  return hipEventCreateWithFlags(e, hipEventDisableTiming);
 }
 
 int block_count(int n, int B) {
@@ -72,8 +98,26 @@ struct Timer {
 };
 Timer g_timer;
 
+// roctx range of a phase, visible to rocprofv3 --marker-trace; host-side
+// markers only (none in calls that must not create objects).
+const char* const kPhaseNames[MSGPM_TIMER_KINDS] = {
+    "msgpm features", "msgpm init", "msgpm eval_cost", "msgpm pm initial pass", "msgpm pm restricted (distorted)",
+    "msgpm ransac", "msgpm assign", "msgpm symmetry", "msgpm fb", "msgpm nnf_update", "msgpm finalize",
+    "msgpm pm lists", "msgpm pm restricted (identity)", "msgpm fill"};
+
+struct Range {
+  bool on;
+  explicit Range(const char* name) : on(!g_no_events) {
+    if (on) roctxRangePushA(name);
+  }
+  ~Range() {
+    if (on) roctxRangePop();
+  }
+};
+
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
+  Range range(kPhaseNames[kind]);
   if (!g_timer.on || g_capturing || g_no_events) return launch();
   std::lock_guard<std::mutex> lk(g_timer.mu);
   hipEvent_t a = g_timer.get(), b = g_timer.get();
@@ -458,6 +502,7 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
                             const int32_t* d_init_nnf1, float* d_flow0, float* d_flow1, uint8_t* d_occ0,
                             uint8_t* d_occ1) {
   msgpm_status st;
+  Range whole("msgpm solve");
 #define RUN(expr, what)                          \
   do {                                           \
     msgpm_status s_ = check((expr), what);       \
@@ -825,13 +870,10 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
       if (g_staging.host) (void)hipHostFree(g_staging.host);
       g_staging.host = nullptr;
       g_staging.cap = 0;
-      if ((st = check(hipHostMalloc(&g_staging.host, plan.bytes, hipHostMallocDefault), "staging")) != MSGPM_OK)
-        return st;
+      if ((st = check(host_alloc(&g_staging.host, plan.bytes), "staging")) != MSGPM_OK) return st;
       g_staging.cap = plan.bytes;
     }
-    if (!g_staging.done && (st = check(hipEventCreateWithFlags(&g_staging.done, hipEventDisableTiming), "staging")) !=
-                               MSGPM_OK)
-      return st;
+    if (!g_staging.done && (st = check(event_create(&g_staging.done), "staging")) != MSGPM_OK) return st;
     char* h = static_cast<char*>(g_staging.host);
     memcpy(h, desc.data(), (size_t)n * sizeof(PairDesc));
     memcpy(h + desc_bytes, items.data(), items.size() * sizeof(Item));
@@ -898,7 +940,7 @@ struct Slot {
   uint64_t bytes = 0;           // workspace footprint counted against the budget
   hipEvent_t done = nullptr;    // recorded after the pair's last launch
   int state = 0;                // 0 queued, 1 active, 2 all launched, 3 finished
-  bool cancelled = false;       // active pair to be dropped at the next round
+  bool cancelled = false;       // cancelled in flight: dropped at the next round, reported as cancelled
 };
 
 }  // namespace
@@ -909,6 +951,7 @@ struct msgpm_server {
   int max_active = 0;
   uint64_t next_ticket = 1;
   uint64_t in_use = 0;
+  int max_queued = 0;              // 0 = no limit
   bool shape_set = false;
   int r = 0, C = 0, fp16 = 0;
   std::deque<Slot*> queue;
@@ -925,6 +968,18 @@ namespace {
 
 uint64_t server_scratch(int max_active) {
   return align256((uint64_t)max_active * sizeof(PairDesc)) + align256((uint64_t)max_active * sizeof(Item));
+}
+
+// At least k completion events ready for reuse (created before any launch of a
+// round, so that a failure leaves the round unlaunched and the state intact).
+msgpm_status reserve_events(msgpm_server* sv, size_t k) {
+  while (sv->events.size() < k) {
+    hipEvent_t e;
+    msgpm_status st = check(event_create(&e), "event");
+    if (st != MSGPM_OK) return st;
+    sv->events.push_back(e);
+  }
+  return MSGPM_OK;
 }
 
 // Marks launched pairs whose completion event has passed as finished and
@@ -1013,7 +1068,12 @@ msgpm_status msgpm_server_submit(msgpm_server* sv, const msgpm_params* p, const 
   q->bytes = L.total_bytes;
   if (q->bytes > sv->budget) {
     delete q;
-    return fail(MSGPM_E_INVALID, "workspace of %llu bytes exceeds the budget", (unsigned long long)L.total_bytes);
+    return fail(MSGPM_E_OOM, "workspace of %llu bytes exceeds the budget of %llu", (unsigned long long)L.total_bytes,
+                (unsigned long long)sv->budget);
+  }
+  if (sv->max_queued > 0 && (int)sv->queue.size() >= sv->max_queued) {
+    delete q;
+    return fail(MSGPM_E_BUSY, "queue full (%d pairs waiting)", (int)sv->queue.size());
   }
   memset(&q->desc, 0, sizeof q->desc);
   q->desc.P = q->P;
@@ -1044,16 +1104,14 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   // cancelled in-flight pairs leave the round; their budget returns once the
   // work already enqueued for them has passed
   {
+    size_t ncancel = 0;
+    for (Slot* q : sv->active) ncancel += q->cancelled ? 1 : 0;
+    if ((st = reserve_events(sv, ncancel)) != MSGPM_OK) return st;
     std::vector<Slot*> keep;
     for (Slot* q : sv->active) {
       if (!q->cancelled) {
         keep.push_back(q);
         continue;
-      }
-      if (sv->events.empty()) {
-        hipEvent_t e;
-        if ((st = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != MSGPM_OK) return st;
-        sv->events.push_back(e);
       }
       q->done = sv->events.back();
       sv->events.pop_back();
@@ -1074,6 +1132,12 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   const int n = (int)sv->active.size();
   if (pending) *pending = n + (int)sv->queue.size();
   if (n == 0) return MSGPM_OK;
+  {
+    // completion events of the pairs whose last step this round launches
+    size_t nlast = 0;
+    for (Slot* q : sv->active) nlast += q->cursor + 1 == q->steps.size() ? 1 : 0;
+    if ((st = reserve_events(sv, nlast)) != MSGPM_OK) return st;
+  }
   // group the active pairs by the kind of their next step; one launch per kind
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -1120,11 +1184,10 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
     sv->host[r] = nullptr;
     sv->cap[r] = 0;
     const size_t want = server_scratch(sv->max_active);
-    if ((st = check(hipHostMalloc(&sv->host[r], want, hipHostMallocDefault), "staging")) != MSGPM_OK) return st;
+    if ((st = check(host_alloc(&sv->host[r], want), "staging")) != MSGPM_OK) return st;
     sv->cap[r] = want;
   }
-  if (!sv->up[r] && (st = check(hipEventCreateWithFlags(&sv->up[r], hipEventDisableTiming), "staging")) != MSGPM_OK)
-    return st;
+  if (!sv->up[r] && (st = check(event_create(&sv->up[r]), "staging")) != MSGPM_OK) return st;
   char* h = static_cast<char*>(sv->host[r]);
   for (int i = 0; i < n; ++i) memcpy(h + (size_t)i * sizeof(PairDesc), &sv->active[i]->desc, sizeof(PairDesc));
   memcpy(h + desc_bytes, items.data(), (size_t)n * sizeof(Item));
@@ -1148,12 +1211,7 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
       still.push_back(q);
       continue;
     }
-    if (sv->events.empty()) {
-      hipEvent_t e;
-      if ((st = check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != MSGPM_OK) return st;
-      sv->events.push_back(e);
-    }
-    q->done = sv->events.back();
+    q->done = sv->events.back();  // reserved above
     sv->events.pop_back();
     if ((st = check(hipEventRecord(q->done, s), "event")) != MSGPM_OK) return st;
     q->state = 2;
@@ -1182,6 +1240,51 @@ msgpm_status msgpm_server_cancel(msgpm_server* sv, uint64_t ticket, int* retired
   } else if (q->state == 1) {
     q->cancelled = true;
   }
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_set_queue_limit(msgpm_server* sv, int max_queued) {
+  if (!sv || max_queued < 0) return fail(MSGPM_E_INVALID, "server is NULL or limit negative");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->max_queued = max_queued;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_wait(msgpm_server* sv, uint64_t ticket, int64_t timeout_us) {
+  if (!sv) return fail(MSGPM_E_INVALID, "server is NULL");
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      auto f = sv->slots.find(ticket);
+      if (f == sv->slots.end()) return fail(MSGPM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+      Slot* q = f->second;
+      if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
+        q->state = 3;
+        sv->in_use -= q->bytes;
+      }
+      if (q->state == 3) {
+        const bool cancelled = q->cancelled;
+        sv->events.push_back(q->done);
+        sv->slots.erase(f);
+        delete q;
+        if (cancelled) return fail(MSGPM_E_CANCELLED, "ticket %llu was cancelled", (unsigned long long)ticket);
+        return MSGPM_OK;
+      }
+    }
+    const int64_t waited =
+        std::chrono::duration_cast<std::chrono::microseconds>(std::chrono::steady_clock::now() - t0).count();
+    if (timeout_us >= 0 && waited >= timeout_us)
+      return fail(MSGPM_E_TIMEOUT, "ticket %llu not done after %lld us", (unsigned long long)ticket,
+                  (long long)waited);
+    int64_t nap = 50;
+    if (timeout_us >= 0 && timeout_us - waited < nap) nap = timeout_us - waited;
+    std::this_thread::sleep_for(std::chrono::microseconds(nap));
+  }
+}
+
+msgpm_status msgpm_debug_fail_allocations(int n) {
+  g_fail_allocs.store(n > 0 ? n : 0);
   return MSGPM_OK;
 }
 

@@ -23,7 +23,9 @@ FLAG_HISTEQ = 8       # equalise the frames' HSV value channel before the featur
 FLAG_MERGE_STRICT = 16  # strict level priority: a later level assigns only unassigned pixels
 PM_FRESH = 2          # pm_halfsweep: compute each swept pixel's current cost first (folds the cost refresh in)
 
-STATUS = {0: "OK", 1: "E_INVALID", 3: "E_DEVICE", 4: "E_UNSUPPORTED"}
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_DEVICE", 4: "E_UNSUPPORTED", 5: "E_BUSY", 6: "E_CANCELLED",
+          7: "E_TIMEOUT"}
+E_INVALID, E_OOM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_CANCELLED, E_TIMEOUT = 1, 2, 3, 4, 5, 6, 7
 
 
 class MsgpmError(RuntimeError):
@@ -109,6 +111,9 @@ def lib() -> ctypes.CDLL:
             "msgpm_server_step": [vp, vp, vp, ctypes.POINTER(i)],
             "msgpm_server_poll": [vp, u64, ctypes.POINTER(i)],
             "msgpm_server_cancel": [vp, u64, ctypes.POINTER(i)],
+            "msgpm_server_wait": [vp, u64, ctypes.c_int64],
+            "msgpm_server_set_queue_limit": [vp, i],
+            "msgpm_debug_fail_allocations": [i],
         }.items():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = ctypes.c_int
@@ -336,6 +341,11 @@ def solve_static(p: Params, rgb1, rgb2, flows, occs, planes=None, init0=None, in
           _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _ptr(planes), _stream())
 
 
+def debug_fail_allocations(n: int):
+    """Test hook: the library's next n own allocations fail (E_OOM)."""
+    _call("msgpm_debug_fail_allocations", int(n))
+
+
 def solve(frame1, frame2, **params):
     """One-shot solve of a frame pair (numpy or torch HWC float32 frames)."""
     H, W = frame1.shape[:2]
@@ -424,6 +434,15 @@ class Server:
         d = ctypes.c_int()
         _call("msgpm_server_poll", self.h, int(ticket), ctypes.byref(d))
         return bool(d.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """msgpm_server_wait: returns once the pair is done (ticket retired);
+        raises MsgpmError with status E_TIMEOUT (ticket still valid) or
+        E_CANCELLED (retired)."""
+        _call("msgpm_server_wait", self.h, int(ticket), int(timeout_us))
+
+    def set_queue_limit(self, max_queued: int):
+        _call("msgpm_server_set_queue_limit", self.h, int(max_queued))
 
     def cancel(self, ticket: int) -> bool:
         """Cancels a pair; True if it was still queued and is gone already (an

@@ -254,7 +254,8 @@ def _random_motion(rng, cx, cy, tmax, persp=2e-5):
 
 def planar_pair(W: int = 1024, H: int = 436, seed: int = 0, n_quads: int = 20, cam_t: float = 30.0,
                 rel_t: float = 12.0, fg_t: float = 40.0, fg_occ: tuple = (0.045, 0.055),
-                gain_range: tuple = (0.8, 1.2), max_tries: int = 400, scale: float = 1.0) -> Pair:
+                gain_range: tuple = (0.8, 1.2), max_tries: int = 400, scale: float = 1.0,
+                independent: bool = False) -> Pair:
     """Piecewise-planar scene shaped like the paper's 1024x436 frames.
 
     * camera: a perspective similarity of the whole frame about its centre
@@ -269,15 +270,29 @@ def planar_pair(W: int = 1024, H: int = 436, seed: int = 0, n_quads: int = 20, c
       quad lies in fg_occ;
     * frame 2 multiplied by a global gain drawn from gain_range.
     scale multiplies every length (radii, translations) for smaller instances.
+
+    independent: the ranges written per quad instead, each motion drawn on its
+    own and not relative to the camera: the background and every quad get a
+    perspective similarity about their centre with translation up to 100 px,
+    scale 0.9-1.1, rotation up to 10 degrees and perspective terms up to 2e-5
+    (quads moving apart or across each other occlude far more of the frame
+    than the foreground quads alone).
     """
     cam_t, rel_t, fg_t = cam_t * scale, rel_t * scale, fg_t * scale
     rng = np.random.default_rng(seed)
-    cam = similarity_about(W / 2, H / 2, rng.uniform(0.95, 1.05), rng.uniform(-5, 5), rng.uniform(-cam_t, cam_t),
-                           rng.uniform(-cam_t, cam_t), rng.uniform(-2e-5, 2e-5), rng.uniform(-2e-5, 2e-5))
+    if independent:
+        cam = _random_motion(rng, W / 2, H / 2, 100.0 * scale)
+    else:
+        cam = similarity_about(W / 2, H / 2, rng.uniform(0.95, 1.05), rng.uniform(-5, 5),
+                               rng.uniform(-cam_t, cam_t), rng.uniform(-cam_t, cam_t), rng.uniform(-2e-5, 2e-5),
+                               rng.uniform(-2e-5, 2e-5))
     layers = [Layer(H=cam)]
     for _ in range(n_quads):
         q = _random_convex_quad(rng, W, H, 40 * scale, 160 * scale)
         c = q.mean(axis=0)
+        if independent:
+            layers.append(Layer(H=_random_motion(rng, c[0], c[1], 100.0 * scale), poly=q))
+            continue
         rel = similarity_about(c[0], c[1], rng.uniform(0.97, 1.03), rng.uniform(-3, 3), rng.uniform(-rel_t, rel_t),
                                rng.uniform(-rel_t, rel_t))
         layers.append(Layer(H=cam @ rel, poly=q))

@@ -156,3 +156,35 @@ def test_served_fp16_pairs_against_oracle():
     for k, (pr, p) in enumerate(scenes):
         g, flows, occs = done[k]
         _against_oracle(pr, p, g, flows, occs)
+
+
+def test_serving_wait_status_codes():
+    """msgpm_server_wait: E_TIMEOUT while a pair is still being launched (the
+    ticket stays valid), OK once its work has completed (outputs equal to the
+    pair solved alone), E_CANCELLED for a pair cancelled in flight; the budget
+    of both returns."""
+    msgpm = _need_gpu()
+    pr, p = _scenes()[0]
+    H, W = pr.shape
+    alone_g = msgpm.Pair(W, H, **p)
+    alone = _outputs(alone_g, *alone_g.solve(pr.frame1, pr.frame2))
+    srv = msgpm.Server(hbm_budget=1 << 34, max_active=4)
+    keep = srv.submit(msgpm.Pair(W, H, **p), pr.frame1, pr.frame2)
+    drop = srv.submit(msgpm.Pair(W, H, **dict(p, seed=3)), pr.frame1, pr.frame2)
+    for _ in range(5):
+        srv.step()
+    with pytest.raises(msgpm.MsgpmError) as e:
+        srv.wait(keep, 1000)
+    assert e.value.status == msgpm.E_TIMEOUT
+    assert not srv.poll(keep)
+    assert not srv.cancel(drop)          # in flight: dropped at the next round
+    while srv.step():
+        pass
+    srv.wait(keep, 10_000_000)
+    g, flows, occs = srv.result(keep)
+    _same(alone, _outputs(g, flows, occs))
+    with pytest.raises(msgpm.MsgpmError) as e:
+        srv.wait(drop, 10_000_000)
+    assert e.value.status == msgpm.E_CANCELLED
+    srv.jobs.pop(drop, None)
+    srv.close()

@@ -1,0 +1,118 @@
+"""Failure paths of the C ABI that the host can force (CPU only, no GPU work):
+requests that can never fit a serving budget (E_OOM), a full queue (E_BUSY,
+transient: the same submission succeeds once there is room), waits that time
+out (E_TIMEOUT, the ticket stays valid), cancellation of a queued pair, an
+injected failure of the library's own allocations (E_OOM with nothing
+enqueued), and calls without a device (E_DEVICE).
+
+The device pointers passed here are 256-byte-aligned placeholders: every call
+below either fails or stops before the first device access, which is what
+each test checks."""
+import ctypes
+import time
+
+import pytest
+import torch
+
+from paper_1804_03787_amd import msgpm
+
+FAKE = 0x10000000  # aligned placeholder address, never dereferenced here
+
+
+def _lib():
+    return msgpm.lib()
+
+
+def _server(budget, max_active=2):
+    h = ctypes.c_void_p()
+    assert _lib().msgpm_server_create(budget, max_active, ctypes.byref(h)) == 0
+    return h
+
+
+def _submit(h, p):
+    t = ctypes.c_uint64()
+    v = ctypes.c_void_p(FAKE)
+    st = _lib().msgpm_server_submit(h, ctypes.byref(p), v, v, None, None, v, v, v, v, v, ctypes.byref(t))
+    return st, t.value
+
+
+def _err():
+    return _lib().msgpm_last_error().decode()
+
+
+def test_server_create_rejects_bad_arguments():
+    h = ctypes.c_void_p()
+    assert _lib().msgpm_server_create(1 << 30, 0, ctypes.byref(h)) == msgpm.E_INVALID
+    assert _lib().msgpm_server_create(1 << 30, 5000, ctypes.byref(h)) == msgpm.E_INVALID
+    assert _lib().msgpm_server_create(1 << 30, 4, None) == msgpm.E_INVALID
+
+
+def test_oversize_request_is_oom_not_busy():
+    p = msgpm.make_params(320, 240, blocks=(32, 16))
+    need = msgpm.layout(p).total_bytes
+    h = _server(need - 1)
+    st, _ = _submit(h, p)
+    assert st == msgpm.E_OOM and "budget" in _err()
+    assert _lib().msgpm_server_destroy(h) == 0
+
+
+def test_full_queue_is_a_transient_refusal_and_waits_time_out():
+    p = msgpm.make_params(64, 48, blocks=(16,))
+    h = _server(1 << 40)
+    assert _lib().msgpm_server_set_queue_limit(h, 2) == 0
+    assert _lib().msgpm_server_set_queue_limit(h, -1) == msgpm.E_INVALID
+    st1, t1 = _submit(h, p)
+    st2, t2 = _submit(h, p)
+    assert st1 == 0 and st2 == 0 and t1 != t2
+    st3, _ = _submit(h, p)
+    assert st3 == msgpm.E_BUSY and "queue full" in _err()
+    # a queued pair is not done: waits time out and leave the ticket valid
+    assert _lib().msgpm_server_wait(h, t1, 0) == msgpm.E_TIMEOUT
+    t0 = time.perf_counter()
+    assert _lib().msgpm_server_wait(h, t1, 3000) == msgpm.E_TIMEOUT
+    assert time.perf_counter() - t0 >= 0.003
+    done = ctypes.c_int(7)
+    assert _lib().msgpm_server_poll(h, t1, ctypes.byref(done)) == 0 and done.value == 0
+    # cancelling a queued pair retires it at once and frees its queue place
+    retired = ctypes.c_int()
+    assert _lib().msgpm_server_cancel(h, t1, ctypes.byref(retired)) == 0 and retired.value == 1
+    assert _lib().msgpm_server_wait(h, t1, 0) == msgpm.E_INVALID and "unknown ticket" in _err()
+    st4, _ = _submit(h, p)
+    assert st4 == 0
+    assert _lib().msgpm_server_wait(h, 987654, 0) == msgpm.E_INVALID
+    assert _lib().msgpm_server_destroy(h) == 0
+
+
+def test_injected_allocation_failure_in_a_round():
+    """The round's staging allocation fails: E_OOM and nothing enqueued (no
+    device is touched); the injection is used up by that one failure."""
+    p = msgpm.make_params(64, 48, blocks=(16,))
+    h = _server(1 << 40)
+    st, _ = _submit(h, p)
+    assert st == 0
+    assert _lib().msgpm_debug_fail_allocations(1) == 0
+    pending = ctypes.c_int()
+    assert _lib().msgpm_server_step(h, ctypes.c_void_p(FAKE), None, ctypes.byref(pending)) == msgpm.E_OOM
+    assert "staging" in _err()
+    assert _lib().msgpm_debug_fail_allocations(0) == 0
+    assert _lib().msgpm_server_destroy(h) == 0
+
+
+def test_injected_allocation_failure_in_a_batch():
+    p = msgpm.make_params(64, 48, blocks=(16,))
+    params = (msgpm.Params * 2)(p, p)
+    nbytes = ctypes.c_uint64()
+    assert _lib().msgpm_batch_query(2, params, ctypes.byref(nbytes)) == 0
+    arr = (ctypes.c_void_p * 2)(FAKE, FAKE)
+    assert _lib().msgpm_debug_fail_allocations(1) == 0
+    st = _lib().msgpm_solve_batch(2, params, arr, arr, None, None, arr, arr, arr, arr, arr, ctypes.c_void_p(FAKE), None)
+    _lib().msgpm_debug_fail_allocations(0)
+    assert st == msgpm.E_OOM
+
+
+@pytest.mark.skipif(torch.cuda.device_count() > 0, reason="checks the behaviour without a device")
+def test_no_device_is_a_device_error():
+    p = msgpm.make_params(64, 48, blocks=(16,))
+    v = ctypes.c_void_p(FAKE)
+    st = _lib().msgpm_solve(ctypes.byref(p), v, v, None, None, v, v, v, v, v, None)
+    assert st == msgpm.E_DEVICE, _err()
