@@ -151,10 +151,18 @@ def run_batched(args) -> int:
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / args.steps
 
+    if args.tuning:
+        msgpm.tuning_set(r=4, C=5, fp16=True, **json.loads(args.tuning))
     pairs16 = [msgpm.Pair(W, H, **dict(full, seed=1000 + i, fp16=True)) for i, (W, H, _, _) in enumerate(scenes)]
     batch = msgpm.Batch(pairs16)
-    t_batch = timed(lambda: batch.solve(f1, f2))
-    print(f"bench: batched {t_batch * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_eager = timed(lambda: batch.solve(f1, f2))
+    t_batch = timed(lambda: batch.solve(f1, f2, graph=True))
+    print(f"bench: batched {t_eager * 1e3:.1f} ms eager, {t_batch * 1e3:.1f} ms as one graph launch "
+          f"(tuning {msgpm.tuning_get(4, 5, True)})", file=sys.stderr, flush=True)
+    if args.batched_only:
+        print(json.dumps({"metric": "flow Mpix/s (batched)", "value": round(mpix / t_batch, 4), "unit": "Mpix/s",
+                          "eager_mpix_s": round(mpix / t_eager, 4), "tuning": msgpm.tuning_get(4, 5, True)}))
+        return 0
     t_one16 = timed(lambda: [g.solve(a, b) for g, a, b in zip(pairs16, f1, f2)])
     del batch, pairs16
     pairs32 = [msgpm.Pair(W, H, **dict(full, seed=1000 + i)) for i, (W, H, _, _) in enumerate(scenes)]
@@ -176,6 +184,9 @@ def run_batched(args) -> int:
                                "12-30 quads, 3-8% occlusion, patch 9x9, C=5, windows 64/32/16, 8 PM iterations, "
                                "256 RANSAC hypotheses, FP16 feature storage",
                    "pairs": args.pairs, "mpix_per_step": round(mpix, 4)},
+        "launch": "one HIP graph per step (msgpm_solve_batch_graph), persistent kernels",
+        "eager_mpix_s": round(mpix / t_eager, 4),
+        "tuning_wg_per_cu": msgpm.tuning_get(4, 5, True),
         "one_at_a_time_fp16_mpix_s": round(mpix / t_one16, 4),
         "one_at_a_time_fp32_mpix_s": round(mpix / t_one32, 4),
         "speedup_vs_fp32_one_at_a_time": round(t_one32 / t_batch, 3),
@@ -294,6 +305,27 @@ def run_serving(args) -> int:
     capacity = mpix / span
     print(f"bench: capacity {capacity:.2f} Mpix/s ({len(cap_reqs)} pairs in {span:.2f} s)", file=sys.stderr,
           flush=True)
+
+    # the same requests as lock-step batches (msgpm_solve_batch_graph), one per
+    # schedule (3-level and 4-level pairs), the second run timed
+    groups = {}
+    for _, c, j in cap_reqs:
+        groups.setdefault(len(SERVE_SIZES[c][2]), []).append((c, j))
+    batches = []
+    for g in groups.values():
+        b = msgpm.Batch([make_pair(c, True) for c, _ in g])
+        batches.append((b, [frames[k][0] for k in g], [frames[k][1] for k in g]))
+    span_b = 0.0
+    for _ in range(2):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for b, a1, a2 in batches:
+            b.solve(a1, a2, graph=True)
+        torch.cuda.synchronize()
+        span_b = time.perf_counter() - tb
+    batched_same = mpix / span_b
+    del batches
+    print(f"bench: the same requests as lock-step batches {batched_same:.2f} Mpix/s", file=sys.stderr, flush=True)
     mean_mpix = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] * w for c, (_, w, _) in enumerate(SERVE_SIZES)) / 1e6
     runs = {}
     for label, rate in (("offered", args.rate), ("stable", 0.6 * capacity / mean_mpix)):
@@ -329,6 +361,7 @@ def run_serving(args) -> int:
                                "storage; continuous batching",
                    "duration_s": args.duration},
         "capacity_mpix_s": round(capacity, 3),
+        "batched_same_requests_mpix_s": round(batched_same, 3),
         "runs": runs,
     }
     print(json.dumps(line))
@@ -357,6 +390,8 @@ def main() -> int:
     ap.add_argument("--batched", action="store_true",
                     help="batched workload: --pairs pairs of uneven sizes per msgpm_solve_batch")
     ap.add_argument("--pairs", type=int, default=48)
+    ap.add_argument("--tuning", type=str, default="", help="batched: JSON of wg_per_cu per class for r=4, C=5, FP16")
+    ap.add_argument("--batched-only", action="store_true", help="batched: skip the one-at-a-time comparisons")
     ap.add_argument("--serving", action="store_true", help="serving workload: Poisson arrivals, continuous batching")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")

@@ -348,22 +348,74 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
                                const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
                                float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
                                void* d_scratch, void* stream);
+/* msgpm_solve_batch as one HIP graph launch.  Every pair-dependent value
+   (descriptors, item lists, launch sizes) is in the table in d_scratch, which
+   is uploaded on each call, and every batched kernel is persistent (a fixed
+   grid per kernel class, see msgpm_tuning), so the graph depends only on the
+   sequence of phases (the shared parameters), the kernel instantiation, the
+   tuning and d_scratch's address (and, for classes tuned one-shot, the
+   pairs' work-item counts): one graph, captured on first use, serves every
+   later batch with that schedule.  Results are
+   identical to msgpm_solve_batch; kernel timing does not see graph launches.
+   msgpm_graph_cache_clear drops these graphs too. */
+msgpm_status msgpm_solve_batch_graph(int n, const msgpm_params* params, const float* const* d_rgb1,
+                                     const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
+                                     const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
+                                     float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                                     void* d_scratch, void* stream);
+
+/* Launch shape of the batched and served forms.  Their kernels can run
+   persistent: a launch then runs wg_per_cu[class] x (compute units) resident
+   workgroups of 256 threads, which take the launch's work items (tiles of a
+   pair's pixels, windows of a level) in turn; 0 gives one workgroup per work
+   item instead (for the PatchMatch classes a separate form of the kernel
+   without the loop).  Classes: identity-patch PatchMatch (and its cost
+   refresh), distorted-patch PatchMatch, RANSAC, every other per-pixel kernel.
+   Values 0..64; defaults {0, 0, 0, 16}.  Results do not depend on them
+   (every work item is computed the same way wherever it runs).  With every
+   class persistent a batched graph depends only on the schedule (see
+   msgpm_solve_batch_graph); a one-shot class makes it depend on the pairs'
+   work-item counts as well.  A setting applies to one kernel instantiation (patch radius,
+   channel count, storage) or, with 0 / 0 / -1 there, to all that have none
+   of their own; paper_1804_03787_amd/autotune.py measures them per
+   instantiation and the Python binding installs its stored choices.
+   Process-wide; graphs already captured keep the shape they were captured
+   with. */
+enum { MSGPM_TUNE_PM_IDENTITY = 0, MSGPM_TUNE_PM_DISTORTED = 1, MSGPM_TUNE_RANSAC = 2, MSGPM_TUNE_PIXEL = 3,
+       MSGPM_TUNE_CLASSES = 4 };
+typedef struct msgpm_tuning {
+  int32_t patch_radius;  /* 1..4, or 0: any */
+  int32_t channels;      /* 3 or 5, or 0: any */
+  int32_t fp16;          /* 0 or 1, or -1: either storage */
+  int32_t wg_per_cu[MSGPM_TUNE_CLASSES];
+} msgpm_tuning;
+/* Stores t's shape for its instantiation (replacing an earlier one). */
+msgpm_status msgpm_tuning_set(const msgpm_tuning* t);
+/* Fills t->wg_per_cu with the shape that applies to t's instantiation. */
+msgpm_status msgpm_tuning_get(msgpm_tuning* t);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of pairs that arrive at different times.  A
  * server queues submitted pairs and admits them, first come first served,
  * while the sum of the admitted pairs' workspace bytes stays within
  * hbm_budget and at most max_active are in flight.  Each msgpm_server_step
- * issues one scheduling round on `stream`: the in-flight pairs are grouped by
- * the kind of their next pipeline step and every group becomes one batched
- * launch (pairs at different iterations, levels or stages share it), after
- * which each pair has advanced by one step.  A pair's results (as msgpm_solve,
- * and identical to them) are complete once msgpm_server_poll reports it done;
- * its ticket is then retired.  All pairs of a server share patch_radius,
- * channels and the FP16 flag.  Buffers are caller-owned and must stay valid
- * until the pair is done; d_scratch (msgpm_server_scratch_bytes for
- * max_active, 256-byte aligned) holds each round's launch tables.  One host
- * thread at a time per server (calls are serialised by a lock).
+ * first retires the cohorts whose work has completed, then admits the queued
+ * pairs that fit (those sharing the oldest pair's schedule, as a batch must)
+ * as one cohort and enqueues the cohort's whole pipeline: its table is
+ * uploaded and the batched pipeline of msgpm_solve_batch_graph runs as one
+ * graph launch (one graph per schedule and region, captured once), on one of
+ * the server's own streams, ordered after the work already on `stream`.  Up to
+ * four cohorts run on the device side by side, so pairs that arrive while
+ * others are on the GPU start at once and share it with them.  A pair's
+ * results (as msgpm_solve, and identical to them) are complete once
+ * msgpm_server_poll reports it done or msgpm_server_wait returns; its ticket
+ * is then retired.  All pairs of a server share patch_radius, channels and the
+ * FP16 flag; a pipeline of more than 4096 launches (very long fillings or
+ * iteration counts) is not served (MSGPM_E_UNSUPPORTED).  Buffers are
+ * caller-owned and must stay valid until the pair is done; d_scratch
+ * (msgpm_server_scratch_bytes for max_active, 256-byte aligned) holds the
+ * cohorts' tables, in four regions.  One host thread at a time per server
+ * (calls are serialised by a lock).
  * ------------------------------------------------------------------------- */
 typedef struct msgpm_server msgpm_server;
 msgpm_status msgpm_server_create(uint64_t hbm_budget, int max_active, msgpm_server** out);
@@ -379,7 +431,7 @@ msgpm_status msgpm_server_submit(msgpm_server* server, const msgpm_params* p, co
                                  uint64_t* ticket);
 /* Largest number of pairs waiting for admission (0 = no limit, the default). */
 msgpm_status msgpm_server_set_queue_limit(msgpm_server* server, int max_queued);
-/* *pending: pairs queued or still being launched after this round. */
+/* *pending: pairs queued or not yet done after this step. */
 msgpm_status msgpm_server_step(msgpm_server* server, void* d_scratch, void* stream, int* pending);
 msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done);
 /* Waits until the pair's work has completed on the device, then retires the
@@ -392,11 +444,10 @@ msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done)
    thread.  Unknown ticket: MSGPM_E_INVALID. */
 msgpm_status msgpm_server_wait(msgpm_server* server, uint64_t ticket, int64_t timeout_us);
 /* Cancels a pair.  Queued: removed at once, its ticket retired (*retired = 1,
-   may be NULL).  In flight: it takes part in no further round; the next
-   msgpm_server_step marks the end of the work already enqueued for it, after
-   which msgpm_server_poll reports it done (its outputs are then undefined) and
-   its budget is released; its buffers may be written until then.  Fully
-   launched: no effect, the pair completes normally. */
+   may be NULL).  In flight: its cohort's work is already enqueued and runs to
+   its end (the buffers are written until the pair is done); it is then
+   reported done by msgpm_server_poll and cancelled by msgpm_server_wait, and
+   its budget is released with its cohort's. */
 msgpm_status msgpm_server_cancel(msgpm_server* server, uint64_t ticket, int* retired);
 
 /* Test hook for the failure paths: the next n allocations the library itself

@@ -54,10 +54,22 @@ struct Ws {
 
 // Batched launches: one launch covers the same phase of several frame pairs.
 // A pair is described by a PairDesc (its parameters, workspace and buffers);
-// its share of a launch is an Item: workgroups [start, start + nb) of the grid
-// (start a multiple of kXcds, so that XCD-aware remaps within a pair stay
-// valid; the workgroups up to the next item's start exit) and the phase's
-// arguments.
+// its share of a launch is an Item: virtual workgroups [start, start + nb) of
+// the launch (start a multiple of kXcds, so that XCD-aware remaps within a
+// pair stay valid; the virtual workgroups up to the next item's start do
+// nothing).  The phase's arguments are the same for every pair of a launch
+// and are passed by value (BArgs).  Launches are persistent: gridDim.x
+// resident workgroups (a multiple of kXcds) take the `total` virtual
+// workgroups in turn, so one launch per phase serves every window, tile and
+// pair whatever their number.
+//
+// Everything that depends on the pairs (their number, descriptors, items and
+// the launch totals) lives in a table in device memory, so that a kernel's
+// arguments (the table, the launch's index in it, the phase arguments) and
+// its grid depend only on the sequence of phases: a captured graph of a
+// sequence serves any set of pairs that follows it.  Table layout (byte
+// offsets from its base): BatchHead, then LaunchTab[n_launches], then the
+// PairDesc array at desc_off, then the item lists.
 struct PairDesc {
   DevParams P;
   Ws w;
@@ -68,8 +80,31 @@ struct PairDesc {
 };
 struct Item {
   int pair, start, nb;
+};
+struct BArgs {
   int a[5];
 };
+struct BatchHead {
+  int n_launches, n_pairs;
+  uint32_t desc_off;
+  int pad;
+};
+struct LaunchTab {
+  int total;       // virtual workgroups
+  uint32_t items;  // byte offset of the launch's item list (n_pairs items)
+};
+// A launch's view of its table.
+struct BatchView {
+  const PairDesc* pd;
+  const Item* it;
+  int n, total;
+};
+__device__ inline BatchView batch_view(const uint8_t* __restrict__ tab, int k) {
+  const BatchHead* h = reinterpret_cast<const BatchHead*>(tab);
+  const LaunchTab* L = reinterpret_cast<const LaunchTab*>(tab + sizeof(BatchHead)) + k;
+  return BatchView{reinterpret_cast<const PairDesc*>(tab + h->desc_off),
+                   reinterpret_cast<const Item*>(tab + L->items), h->n_pairs, L->total};
+}
 
 // Workgroup coordinates within its pair's part of a launch.
 struct Blk {
@@ -77,9 +112,8 @@ struct Blk {
 };
 __device__ inline Blk blk_here() { return Blk{(int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y}; }
 
-// The item owning this workgroup (items sorted by start; n >= 1).
-__device__ inline int find_item(const Item* __restrict__ it, int n) {
-  const int b = blockIdx.x;
+// The item owning virtual workgroup b (items sorted by start; n >= 1).
+__device__ inline int find_item(const Item* __restrict__ it, int n, int b) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -89,12 +123,31 @@ __device__ inline int find_item(const Item* __restrict__ it, int n) {
   return lo;
 }
 
-// Resolves a batched launch's workgroup: false for a padding workgroup.
-__device__ inline bool batch_blk(const Item* __restrict__ it, int n, int& i, Blk& b) {
-  i = find_item(it, n);
-  const int lb = (int)blockIdx.x - it[i].start;
-  b = Blk{lb, it[i].nb, (int)blockIdx.y};
-  return lb < it[i].nb;
+// Runs body(item, Blk) for every virtual workgroup of a batched launch that
+// belongs to an item, this workgroup taking blockIdx.x, blockIdx.x +
+// gridDim.x, ...  With gridDim.x a multiple of kXcds every virtual workgroup
+// keeps the XCD its index names.  The virtual workgroups of one workgroup
+// come in increasing order, so the owning item is found once and then
+// advanced.  LDS: the whole workgroup synchronises between two virtual
+// workgroups, so a body may use LDS as in a one-shot launch.
+// LOOP = false: the one-shot form, one virtual workgroup per workgroup
+// (gridDim.x >= total), for kernels whose registers the loop would crowd.
+template <bool LDS = false, bool LOOP = true, class F>
+__device__ __forceinline__ void for_each_item(const Item* __restrict__ it, int n, int total, F&& body) {
+  int vb = blockIdx.x;
+  if (vb >= total) return;
+  int i = find_item(it, n, vb);
+  if constexpr (!LOOP) {
+    const int lb = vb - it[i].start;
+    if (lb < it[i].nb) body(i, Blk{lb, it[i].nb, (int)blockIdx.y});
+    return;
+  }
+  for (; vb < total; vb += gridDim.x) {
+    while (i + 1 < n && it[i + 1].start <= vb) ++i;
+    const int lb = vb - it[i].start;
+    if (lb < it[i].nb) body(i, Blk{lb, it[i].nb, (int)blockIdx.y});
+    if (LDS && vb + (int)gridDim.x < total) __syncthreads();
+  }
 }
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -224,15 +277,18 @@ enum BatchKind {
 // Workgroups (x) one pair needs for kernel `kind` with arguments a; grid.y.
 int batch_blocks(int kind, const DevParams& P, const int* a);
 int batch_grid_y(int kind);
-// One batched launch over `total` workgroups; `lds`: dynamic LDS (RANSAC).
-// P0 selects the kernel instantiation (r, C, storage), equal for every pair.
-hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
-                          size_t lds, hipStream_t s);
-hipError_t launch_batched_init(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s);
-hipError_t launch_batched_pm(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
-                             hipStream_t s);
-hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, int n, int total, size_t lds,
-                                 hipStream_t s);
+// Launch k of the table at `tab`, run by `grid` resident workgroups (a
+// multiple of kXcds); `lds`: dynamic LDS (RANSAC).  P0 selects the kernel
+// instantiation (r, C, storage), equal for every pair.  persist = false (the
+// PatchMatch kernels only): the one-shot form, grid >= the launch's total.
+hipError_t launch_batched(int kind, const DevParams& P0, const uint8_t* tab, int k, int grid, size_t lds, BArgs A,
+                          bool persist, hipStream_t s);
+hipError_t launch_batched_init(int kind, const uint8_t* tab, int k, int grid, BArgs A, hipStream_t s);
+hipError_t launch_batched_pm(int kind, const DevParams& P0, const uint8_t* tab, int k, int grid, BArgs A,
+                             bool persist, hipStream_t s);
+hipError_t launch_batched_planes(int kind, const uint8_t* tab, int k, int grid, size_t lds, BArgs A, hipStream_t s);
 size_t ransac_smem_bytes(const DevParams& P, int level);
+// The same for a full B x B window (any frame of at least that size).
+size_t ransac_smem_bytes_window(int B);
 
 }  // namespace msgpm

@@ -536,15 +536,55 @@ msgpm_status solve_sequence(const Ctx& c, const float* d_rgb1, const float* d_rg
   return MSGPM_OK;
 }
 
-// Instantiated graphs of whole pipelines, keyed by the parameters and every
-// buffer address; the oldest is dropped beyond kGraphCache.
-constexpr size_t kGraphCache = 16;
+// Instantiated graphs, keyed by everything their launches depend on (the
+// parameters and buffer addresses of a whole pipeline, or the launch sequence
+// and table address of a batched one); the oldest is dropped beyond
+// kGraphCache.
+constexpr size_t kGraphCache = 64;
 struct GraphCache {
   std::mutex mu;
   std::vector<std::pair<std::string, hipGraphExec_t>> entries;
   hipStream_t capture = nullptr;
 };
 GraphCache g_graphs;
+
+// Launches the graph cached under `key` on s; on a miss, record(stream)
+// enqueues the launches on the library's capture stream, which are captured
+// into the graph first.
+template <class F>
+msgpm_status cached_graph_launch(const std::string& key, hipStream_t s, F&& record) {
+  std::lock_guard<std::mutex> lk(g_graphs.mu);
+  hipGraphExec_t exec = nullptr;
+  for (auto& e : g_graphs.entries)
+    if (e.first == key) exec = e.second;
+  if (!exec) {
+    msgpm_status st;
+    if (!g_graphs.capture &&
+        (st = check(hipStreamCreateWithFlags(&g_graphs.capture, hipStreamNonBlocking), "graph stream")) != MSGPM_OK)
+      return st;
+    if ((st = check(hipStreamBeginCapture(g_graphs.capture, hipStreamCaptureModeThreadLocal), "graph capture")) !=
+        MSGPM_OK)
+      return st;
+    g_capturing = true;
+    const msgpm_status run = record(g_graphs.capture);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    st = check(hipStreamEndCapture(g_graphs.capture, &graph), "graph capture");
+    if (run != MSGPM_OK || st != MSGPM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return run != MSGPM_OK ? run : st;
+    }
+    st = check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    if (st != MSGPM_OK) return st;
+    if (g_graphs.entries.size() >= kGraphCache) {
+      (void)hipGraphExecDestroy(g_graphs.entries.front().second);
+      g_graphs.entries.erase(g_graphs.entries.begin());
+    }
+    g_graphs.entries.emplace_back(key, exec);
+  }
+  return check(hipGraphLaunch(exec, s), "graph launch");
+}
 
 }  // namespace
 
@@ -570,39 +610,13 @@ msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const
   const void* ptrs[] = {d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_ws, d_flow0, d_flow1, d_occ0, d_occ1};
   std::string key(reinterpret_cast<const char*>(p), sizeof *p);
   key.append(reinterpret_cast<const char*>(ptrs), sizeof ptrs);
-  std::lock_guard<std::mutex> lk(g_graphs.mu);
-  hipGraphExec_t exec = nullptr;
-  for (auto& e : g_graphs.entries)
-    if (e.first == key) exec = e.second;
-  if (!exec) {
-    if (!g_graphs.capture &&
-        (st = check(hipStreamCreateWithFlags(&g_graphs.capture, hipStreamNonBlocking), "graph stream")) != MSGPM_OK)
-      return st;
+  Aux* aux = nullptr;  // created outside the capture; joins it through the fork event
+  if ((st = check(aux_stream(&aux), "second stream")) != MSGPM_OK) return st;
+  return cached_graph_launch(key, c.s, [&](hipStream_t cs) {
     Ctx cc = c;
-    cc.s = g_graphs.capture;
-    Aux* aux = nullptr;  // created outside the capture; joins it through the fork event
-    if ((st = check(aux_stream(&aux), "second stream")) != MSGPM_OK) return st;
-    if ((st = check(hipStreamBeginCapture(cc.s, hipStreamCaptureModeThreadLocal), "graph capture")) != MSGPM_OK)
-      return st;
-    g_capturing = true;
-    msgpm_status run = solve_sequence(cc, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_flow0, d_flow1, d_occ0, d_occ1);
-    g_capturing = false;
-    hipGraph_t graph = nullptr;
-    st = check(hipStreamEndCapture(cc.s, &graph), "graph capture");
-    if (run != MSGPM_OK || st != MSGPM_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return run != MSGPM_OK ? run : st;
-    }
-    st = check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(graph);
-    if (st != MSGPM_OK) return st;
-    if (g_graphs.entries.size() >= kGraphCache) {
-      (void)hipGraphExecDestroy(g_graphs.entries.front().second);
-      g_graphs.entries.erase(g_graphs.entries.begin());
-    }
-    g_graphs.entries.emplace_back(key, exec);
-  }
-  return check(hipGraphLaunch(exec, c.s), "graph launch");
+    cc.s = cs;
+    return solve_sequence(cc, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_flow0, d_flow1, d_occ0, d_occ1);
+  });
 }
 
 msgpm_status msgpm_graph_cache_clear(void) {
@@ -744,6 +758,12 @@ std::vector<BatchStep> batch_schedule(const DevParams& P) {
   return v;
 }
 
+// What the pairs of one batched launch sequence must share.
+bool same_schedule(const DevParams& a, const DevParams& b) {
+  return b.r == a.r && b.C == a.C && b.fp16 == a.fp16 && b.iters == a.iters && b.n_levels == a.n_levels &&
+         b.cues == a.cues && b.fill_sweeps == a.fill_sweeps && b.histeq == a.histeq;
+}
+
 // Validates a batch and derives each pair's kernel parameters.
 msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevParams>& P,
                            std::vector<msgpm_layout>& L) {
@@ -754,10 +774,7 @@ msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevPar
   for (int i = 0; i < n; ++i) {
     msgpm_status st = prepare(&params[i], &P[i], &L[i]);
     if (st != MSGPM_OK) return fail(st, "pair %d: %s", i, g_err.c_str());
-    const DevParams& a = P[0];
-    const DevParams& b = P[i];
-    if (b.r != a.r || b.C != a.C || b.fp16 != a.fp16 || b.iters != a.iters || b.n_levels != a.n_levels ||
-        b.cues != a.cues || b.fill_sweeps != a.fill_sweeps || b.histeq != a.histeq)
+    if (!same_schedule(P[0], P[i]))
       return fail(MSGPM_E_INVALID,
                   "pair %d: a batch needs one patch radius, channel count, storage, iteration count, level count, "
                   "set of occlusion cues, filling length and equalisation setting",
@@ -766,45 +783,185 @@ msgpm_status batch_prepare(int n, const msgpm_params* params, std::vector<DevPar
   return MSGPM_OK;
 }
 
-// Item table of one batch: per step, one item per pair.
-struct BatchPlan {
-  std::vector<BatchStep> steps;
-  std::vector<int> total;    // workgroups of each step's launch
-  std::vector<size_t> lds;   // dynamic LDS of each step's launch
-  uint64_t items = 0;        // items of all steps (n per step)
-  uint64_t bytes = 0;        // scratch: descriptors, then items
+// Resident workgroups per compute unit of the persistent batched launches, per
+// class of kernel and kernel instantiation (msgpm_tuning); entry 0 is the
+// default for every instantiation.
+std::mutex g_tune_mu;
+std::vector<msgpm_tuning> g_tune = {msgpm_tuning{0, 0, -1, {0, 0, 0, 16}}};
+
+bool tune_key_valid(const msgpm_tuning& t) {
+  return (t.patch_radius == 0 || (t.patch_radius >= 1 && t.patch_radius <= 4)) &&
+         (t.channels == 0 || t.channels == 3 || t.channels == 5) && (t.fp16 >= -1 && t.fp16 <= 1);
+}
+
+// The shape for instantiation (r, C, fp16): the most specific stored entry.
+msgpm_tuning tune_for(int r, int C, int fp16) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const msgpm_tuning* best = &g_tune[0];
+  int score = -1;
+  for (const msgpm_tuning& t : g_tune) {
+    if ((t.patch_radius && t.patch_radius != r) || (t.channels && t.channels != C) || (t.fp16 >= 0 && t.fp16 != fp16))
+      continue;
+    const int sc = (t.patch_radius != 0) + (t.channels != 0) + (t.fp16 >= 0);
+    if (sc > score) {
+      score = sc;
+      best = &t;
+    }
+  }
+  return *best;
+}
+
+int tune_class(int kind) {
+  switch (kind) {
+    case BK_PM_INIT:
+    case BK_PM_RESTRICTED_IDENT:
+    case BK_EVAL_COST_IDENT:
+      return MSGPM_TUNE_PM_IDENTITY;
+    case BK_PM_RESTRICTED:
+    case BK_EVAL_COST_PLANE:
+      return MSGPM_TUNE_PM_DISTORTED;
+    case BK_RANSAC:
+      return MSGPM_TUNE_RANSAC;
+    default:
+      return MSGPM_TUNE_PIXEL;
+  }
+}
+
+// Compute units of the current device (cached per device; 256 if unknown).
+int device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load();
+  if (v > 0) return v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+  cache[dev].store(v);
+  return v;
+}
+
+// One launch of a plan: its kind and arguments, its item list, its number of
+// virtual workgroups and its grid (independent of the pairs: the resident
+// workgroups of its class).
+struct Launch {
+  int kind, timer;
+  BArgs A;
+  int list, total, grid;
+  bool persist;  // loop over the virtual workgroups (else one each, grid = total)
+  size_t lds;
 };
 
-BatchPlan batch_plan(int n, const std::vector<DevParams>& P, std::vector<Item>* items) {
-  BatchPlan b;
-  b.steps = batch_schedule(P[0]);
-  for (const BatchStep& st : b.steps) {
+struct Plan {
+  int n = 0;
+  std::vector<Launch> launches;
+  std::vector<std::vector<Item>> lists;  // distinct item lists, shared by launches
+  std::vector<uint64_t> list_off;
+  uint64_t desc_off = 0, bytes = 0;
+};
+
+Plan make_plan(int n, const std::vector<DevParams>& P, const msgpm_tuning& t, int cus) {
+  Plan pl;
+  pl.n = n;
+  for (const BatchStep& st : batch_schedule(P[0])) {
+    std::vector<Item> items(n);
     int start = 0;
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
-      Item it;
-      memset(&it, 0, sizeof it);
+      Item& it = items[i];
       it.pair = i;
       it.nb = batch_blocks(st.kind, P[i], st.a);
-      it.start = st.kind == BK_ZERO_ACTIVE ? i : start;
-      for (int k = 0; k < 5; ++k) it.a[k] = st.a[k];
+      it.start = start;
       start += (it.nb + kXcds - 1) / kXcds * kXcds;
       if (st.kind == BK_RANSAC) {
-        const size_t m = ransac_smem_bytes(P[i], st.a[0]);
+        const size_t m = ransac_smem_bytes_window(P[i].block[st.a[0]]);
         lds = m > lds ? m : lds;
       }
-      if (items) items->push_back(it);
     }
-    b.total.push_back(st.kind == BK_ZERO_ACTIVE ? n : start);
-    b.lds.push_back(lds);
+    int list = -1;
+    for (size_t j = 0; j < pl.lists.size() && list < 0; ++j)
+      if (memcmp(pl.lists[j].data(), items.data(), (size_t)n * sizeof(Item)) == 0) list = (int)j;
+    if (list < 0) {
+      list = (int)pl.lists.size();
+      pl.lists.push_back(items);
+    }
+    Launch L;
+    L.kind = st.kind;
+    L.timer = st.timer;
+    for (int k = 0; k < 5; ++k) L.A.a[k] = st.a[k];
+    L.list = list;
+    L.total = start;
+    L.lds = lds;
+    const int w = t.wg_per_cu[tune_class(st.kind)];
+    L.persist = true;
+    if (st.kind == BK_ZERO_ACTIVE) {
+      L.grid = kXcds;
+    } else if (w == 0) {
+      L.grid = start;  // one workgroup per virtual workgroup
+      L.persist = false;
+    } else {
+      const long g = (long)w * cus;
+      L.grid = (int)((g + kXcds - 1) / kXcds * kXcds);
+    }
+    pl.launches.push_back(L);
   }
-  b.items = (uint64_t)b.steps.size() * n;
-  b.bytes = align256((uint64_t)n * sizeof(PairDesc)) + b.items * sizeof(Item);
-  return b;
+  uint64_t off = align256(sizeof(BatchHead) + pl.launches.size() * sizeof(LaunchTab));
+  pl.desc_off = off;
+  off = align256(off + (uint64_t)n * sizeof(PairDesc));
+  for (const auto& l : pl.lists) {
+    pl.list_off.push_back(off);
+    off += (uint64_t)l.size() * sizeof(Item);
+  }
+  pl.bytes = align256(off);
+  return pl;
 }
 
-// Pinned staging buffer for the descriptor upload; reused once the previous
-// upload (recorded by `done`) has completed.
+// The plan's table (header, launch entries, descriptors, item lists) at h.
+void write_tables(const Plan& pl, const PairDesc* desc, char* h) {
+  BatchHead hd;
+  hd.n_launches = (int)pl.launches.size();
+  hd.n_pairs = pl.n;
+  hd.desc_off = (uint32_t)pl.desc_off;
+  hd.pad = 0;
+  memcpy(h, &hd, sizeof hd);
+  LaunchTab* L = reinterpret_cast<LaunchTab*>(h + sizeof(BatchHead));
+  for (size_t k = 0; k < pl.launches.size(); ++k) {
+    L[k].total = pl.launches[k].total;
+    L[k].items = (uint32_t)pl.list_off[pl.launches[k].list];
+  }
+  memcpy(h + pl.desc_off, desc, (size_t)pl.n * sizeof(PairDesc));
+  for (size_t j = 0; j < pl.lists.size(); ++j)
+    memcpy(h + pl.list_off[j], pl.lists[j].data(), pl.lists[j].size() * sizeof(Item));
+}
+
+// The plan's launches on s, reading the table at dev.
+msgpm_status run_plan(const Plan& pl, const DevParams& P0, const uint8_t* dev, hipStream_t s) {
+  for (size_t k = 0; k < pl.launches.size(); ++k) {
+    const Launch& L = pl.launches[k];
+    msgpm_status st = check(
+        timed(L.timer, s, [&] { return launch_batched(L.kind, P0, dev, (int)k, L.grid, L.lds, L.A, L.persist, s); }),
+        "batched launch");
+    if (st != MSGPM_OK) return st;
+  }
+  return MSGPM_OK;
+}
+
+// The plan's launches as one graph launch on s: the graph depends only on the
+// launch sequence, the kernel instantiation and the table's address, so it is
+// captured once and serves any set of pairs with that schedule.
+msgpm_status run_plan_graph(const Plan& pl, const DevParams& P0, const uint8_t* dev, hipStream_t s) {
+  std::string key("batch");
+  const int inst[3] = {P0.r, P0.C, P0.fp16};
+  key.append(reinterpret_cast<const char*>(inst), sizeof inst);
+  key.append(reinterpret_cast<const char*>(&dev), sizeof dev);
+  for (const Launch& L : pl.launches) {
+    const int64_t rec[9] = {L.kind, L.A.a[0], L.A.a[1], L.A.a[2], L.A.a[3], L.A.a[4], L.grid, (int64_t)L.lds,
+                            L.persist};
+    key.append(reinterpret_cast<const char*>(rec), sizeof rec);
+  }
+  return cached_graph_launch(key, s, [&](hipStream_t cs) { return run_plan(pl, P0, dev, cs); });
+}
+
+// Pinned staging buffer for the table upload of msgpm_solve_batch; reused
+// once the previous upload (recorded by `done`) has completed.
 struct Staging {
   std::mutex mu;
   void* host = nullptr;
@@ -813,25 +970,10 @@ struct Staging {
 };
 Staging g_staging;
 
-}  // namespace
-
-extern "C" {
-
-msgpm_status msgpm_batch_query(int n, const msgpm_params* params, uint64_t* scratch_bytes) {
-  if (!scratch_bytes) return fail(MSGPM_E_INVALID, "scratch_bytes is NULL");
-  std::vector<DevParams> P;
-  std::vector<msgpm_layout> L;
-  msgpm_status st = batch_prepare(n, params, P, L);
-  if (st != MSGPM_OK) return st;
-  *scratch_bytes = batch_plan(n, P, nullptr).bytes;
-  return MSGPM_OK;
-}
-
-msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* const* d_rgb1,
-                               const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
-                               const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
-                               float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
-                               void* d_scratch, void* stream) {
+msgpm_status batch_run(int n, const msgpm_params* params, const float* const* d_rgb1, const float* const* d_rgb2,
+                       const int32_t* const* d_init_nnf0, const int32_t* const* d_init_nnf1, void* const* d_ws,
+                       float* const* d_flow0, float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                       void* d_scratch, void* stream, bool graph) {
   std::vector<DevParams> P;
   std::vector<msgpm_layout> L;
   msgpm_status st = batch_prepare(n, params, P, L);
@@ -840,8 +982,6 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
     return fail(MSGPM_E_INVALID, "pointer array is NULL");
   if (!d_scratch || (reinterpret_cast<uintptr_t>(d_scratch) & 255))
     return fail(MSGPM_E_INVALID, "scratch is NULL or not 256-byte aligned");
-  std::vector<Item> items;
-  const BatchPlan plan = batch_plan(n, P, &items);
   std::vector<PairDesc> desc(n);
   for (int i = 0; i < n; ++i) {
     if (!d_ws[i] || (reinterpret_cast<uintptr_t>(d_ws[i]) & 255))
@@ -860,11 +1000,12 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
     desc[i].occ[0] = d_occ0[i];
     desc[i].occ[1] = d_occ1[i];
   }
+  const msgpm_tuning t = tune_for(P[0].r, P[0].C, P[0].fp16);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const uint64_t desc_bytes = align256((uint64_t)n * sizeof(PairDesc));
   char* dev = static_cast<char*>(d_scratch);
   {
     std::lock_guard<std::mutex> lk(g_staging.mu);
+    const Plan plan = make_plan(n, P, t, 256);  // the table's size does not depend on the grids
     if (g_staging.done && (st = check(hipEventSynchronize(g_staging.done), "staging")) != MSGPM_OK) return st;
     if (g_staging.cap < plan.bytes) {
       if (g_staging.host) (void)hipHostFree(g_staging.host);
@@ -874,23 +1015,70 @@ msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* c
       g_staging.cap = plan.bytes;
     }
     if (!g_staging.done && (st = check(event_create(&g_staging.done), "staging")) != MSGPM_OK) return st;
-    char* h = static_cast<char*>(g_staging.host);
-    memcpy(h, desc.data(), (size_t)n * sizeof(PairDesc));
-    memcpy(h + desc_bytes, items.data(), items.size() * sizeof(Item));
-    if ((st = check(hipMemcpyAsync(dev, h, plan.bytes, hipMemcpyHostToDevice, s), "upload")) != MSGPM_OK) return st;
+    const Plan run = make_plan(n, P, t, device_cus());
+    write_tables(run, desc.data(), static_cast<char*>(g_staging.host));
+    if ((st = check(hipMemcpyAsync(dev, g_staging.host, run.bytes, hipMemcpyHostToDevice, s), "upload")) != MSGPM_OK)
+      return st;
     if ((st = check(hipEventRecord(g_staging.done, s), "staging")) != MSGPM_OK) return st;
+    const uint8_t* tab = reinterpret_cast<const uint8_t*>(dev);
+    return graph ? run_plan_graph(run, P[0], tab, s) : run_plan(run, P[0], tab, s);
   }
-  const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
-  const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
-  auto step = [&](size_t k, hipStream_t q) {
-    const BatchStep& bs = plan.steps[k];
-    return check(timed(bs.timer, q, [&] { return launch_batched(bs.kind, P[0], pd, it + k * n, n, plan.total[k], plan.lds[k], q); }),
-                 "batched launch");
-  };
-  // one launch per step on the caller's stream: with many pairs per launch the two
-  // restricted kinds gain nothing from running side by side (measured)
-  for (size_t k = 0; k < plan.steps.size(); ++k)
-    if ((st = step(k, s)) != MSGPM_OK) return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+msgpm_status msgpm_batch_query(int n, const msgpm_params* params, uint64_t* scratch_bytes) {
+  if (!scratch_bytes) return fail(MSGPM_E_INVALID, "scratch_bytes is NULL");
+  std::vector<DevParams> P;
+  std::vector<msgpm_layout> L;
+  msgpm_status st = batch_prepare(n, params, P, L);
+  if (st != MSGPM_OK) return st;
+  *scratch_bytes = make_plan(n, P, tune_for(P[0].r, P[0].C, P[0].fp16), 256).bytes;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_solve_batch(int n, const msgpm_params* params, const float* const* d_rgb1,
+                               const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
+                               const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
+                               float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                               void* d_scratch, void* stream) {
+  return batch_run(n, params, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_ws, d_flow0, d_flow1, d_occ0, d_occ1,
+                   d_scratch, stream, false);
+}
+
+msgpm_status msgpm_solve_batch_graph(int n, const msgpm_params* params, const float* const* d_rgb1,
+                                     const float* const* d_rgb2, const int32_t* const* d_init_nnf0,
+                                     const int32_t* const* d_init_nnf1, void* const* d_ws, float* const* d_flow0,
+                                     float* const* d_flow1, uint8_t* const* d_occ0, uint8_t* const* d_occ1,
+                                     void* d_scratch, void* stream) {
+  return batch_run(n, params, d_rgb1, d_rgb2, d_init_nnf0, d_init_nnf1, d_ws, d_flow0, d_flow1, d_occ0, d_occ1,
+                   d_scratch, stream, true);
+}
+
+msgpm_status msgpm_tuning_set(const msgpm_tuning* t) {
+  if (!t) return fail(MSGPM_E_INVALID, "tuning is NULL");
+  if (!tune_key_valid(*t)) return fail(MSGPM_E_INVALID, "tuning instantiation (r, C, fp16) invalid");
+  for (int c = 0; c < MSGPM_TUNE_CLASSES; ++c)
+    if (t->wg_per_cu[c] < 0 || t->wg_per_cu[c] > 64)
+      return fail(MSGPM_E_INVALID, "wg_per_cu[%d] = %d outside 0..64", c, t->wg_per_cu[c]);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (msgpm_tuning& e : g_tune)
+    if (e.patch_radius == t->patch_radius && e.channels == t->channels && e.fp16 == t->fp16) {
+      e = *t;
+      return MSGPM_OK;
+    }
+  if (g_tune.size() >= 64) return fail(MSGPM_E_INVALID, "too many tuning entries");
+  g_tune.push_back(*t);
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_tuning_get(msgpm_tuning* t) {
+  if (!t) return fail(MSGPM_E_INVALID, "tuning is NULL");
+  if (!tune_key_valid(*t)) return fail(MSGPM_E_INVALID, "tuning instantiation (r, C, fp16) invalid");
+  const msgpm_tuning f = tune_for(t->patch_radius, t->channels, t->fp16);
+  for (int c = 0; c < MSGPM_TUNE_CLASSES; ++c) t->wg_per_cu[c] = f.wg_per_cu[c];
   return MSGPM_OK;
 }
 
@@ -928,20 +1116,40 @@ msgpm_status msgpm_timing_read(double* ms, int64_t* launches) {
 
 }  // extern "C"
 
-// ---- serving: continuous batching of pairs at different steps ----------------
+// ---- serving: continuous batching in cohorts ----------------------------------
+// Each msgpm_server_step admits the queued pairs that fit (first come, first
+// served, one schedule per cohort) as one cohort and enqueues its whole
+// pipeline as one batched graph launch on one of the server's streams; up to
+// kCohorts cohorts run on the device side by side, each with its own region
+// of the caller's scratch for its table.
 namespace {
+
+constexpr int kCohorts = 4;          // cohorts in flight (and server streams)
+constexpr int kMaxLaunches = 4096;   // launches of one pipeline a region holds
+constexpr int kMaxLists = 48;        // distinct item lists of one pipeline
 
 struct Slot {
   uint64_t ticket = 0;
   DevParams P;
   PairDesc desc;
-  std::vector<BatchStep> steps;
-  size_t cursor = 0;
-  uint64_t bytes = 0;           // workspace footprint counted against the budget
-  hipEvent_t done = nullptr;    // recorded after the pair's last launch
-  int state = 0;                // 0 queued, 1 active, 2 all launched, 3 finished
-  bool cancelled = false;       // cancelled in flight: dropped at the next round, reported as cancelled
+  uint64_t bytes = 0;     // workspace footprint counted against the budget
+  int state = 0;          // 0 queued, 1 in flight, 3 finished
+  int cohort = -1;        // while in flight
+  bool cancelled = false; // reported as cancelled when finished
 };
+
+struct Cohort {
+  bool busy = false;
+  std::vector<Slot*> pairs;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+  void* host = nullptr;  // pinned staging of its table
+};
+
+uint64_t region_bytes(int max_active) {
+  return align256(sizeof(BatchHead) + (uint64_t)kMaxLaunches * sizeof(LaunchTab)) +
+         align256((uint64_t)max_active * sizeof(PairDesc)) + align256((uint64_t)kMaxLists * max_active * sizeof(Item));
+}
 
 }  // namespace
 
@@ -949,49 +1157,54 @@ struct msgpm_server {
   std::mutex mu;
   uint64_t budget = 0;
   int max_active = 0;
+  int max_queued = 0;  // 0 = no limit
   uint64_t next_ticket = 1;
   uint64_t in_use = 0;
-  int max_queued = 0;              // 0 = no limit
+  int in_flight = 0;
   bool shape_set = false;
   int r = 0, C = 0, fp16 = 0;
   std::deque<Slot*> queue;
-  std::vector<Slot*> active;
   std::map<uint64_t, Slot*> slots;
-  std::vector<hipEvent_t> events;  // completion events to reuse
-  void* host[2] = {nullptr, nullptr};
-  size_t cap[2] = {0, 0};
-  hipEvent_t up[2] = {nullptr, nullptr};
-  int ring = 0;
+  Cohort cohorts[kCohorts];
+  int next = 0;  // cohort region tried first
 };
 
 namespace {
 
-uint64_t server_scratch(int max_active) {
-  return align256((uint64_t)max_active * sizeof(PairDesc)) + align256((uint64_t)max_active * sizeof(Item));
+// Finishes the cohorts whose work has completed: their pairs are done and
+// their budget is free.
+void server_retire(msgpm_server* sv) {
+  for (Cohort& c : sv->cohorts) {
+    if (!c.busy || hipEventQuery(c.done) != hipSuccess) continue;
+    for (Slot* q : c.pairs) {
+      q->state = 3;
+      q->cohort = -1;
+      sv->in_use -= q->bytes;
+      --sv->in_flight;
+    }
+    c.pairs.clear();
+    c.busy = false;
+  }
 }
 
-// At least k completion events ready for reuse (created before any launch of a
-// round, so that a failure leaves the round unlaunched and the state intact).
-msgpm_status reserve_events(msgpm_server* sv, size_t k) {
-  while (sv->events.size() < k) {
-    hipEvent_t e;
-    msgpm_status st = check(event_create(&e), "event");
-    if (st != MSGPM_OK) return st;
-    sv->events.push_back(e);
-  }
+// The cohort's objects, created on its first use (so that a failure leaves
+// nothing enqueued): pinned staging, events, stream.
+msgpm_status cohort_objects(msgpm_server* sv, Cohort& c) {
+  msgpm_status st;
+  if (!c.host && (st = check(host_alloc(&c.host, region_bytes(sv->max_active)), "staging")) != MSGPM_OK) return st;
+  if (!c.fork && (st = check(event_create(&c.fork), "event")) != MSGPM_OK) return st;
+  if (!c.done && (st = check(event_create(&c.done), "event")) != MSGPM_OK) return st;
+  if (!c.s && (st = check(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking), "server stream")) != MSGPM_OK)
+    return st;
   return MSGPM_OK;
 }
 
-// Marks launched pairs whose completion event has passed as finished and
-// releases their budget.
-void server_retire(msgpm_server* sv) {
-  for (auto& kv : sv->slots) {
-    Slot* q = kv.second;
-    if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
-      q->state = 3;
-      sv->in_use -= q->bytes;
-    }
-  }
+// Retires a finished ticket; true if it was cancelled.
+bool server_forget(msgpm_server* sv, std::map<uint64_t, Slot*>::iterator f) {
+  const bool cancelled = f->second->cancelled;
+  delete f->second;
+  sv->slots.erase(f);
+  return cancelled;
 }
 
 }  // namespace
@@ -1012,29 +1225,22 @@ msgpm_status msgpm_server_destroy(msgpm_server* sv) {
   if (!sv) return MSGPM_OK;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    for (auto& kv : sv->slots) {
-      if (kv.second->done) {
-        (void)hipEventSynchronize(kv.second->done);
-        (void)hipEventDestroy(kv.second->done);
-      }
-      delete kv.second;
+    for (Cohort& c : sv->cohorts) {
+      if (c.busy) (void)hipEventSynchronize(c.done);
+      if (c.done) (void)hipEventDestroy(c.done);
+      if (c.fork) (void)hipEventDestroy(c.fork);
+      if (c.s) (void)hipStreamDestroy(c.s);
+      if (c.host) (void)hipHostFree(c.host);
     }
-    for (hipEvent_t e : sv->events) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k) {
-      if (sv->up[k]) {
-        (void)hipEventSynchronize(sv->up[k]);
-        (void)hipEventDestroy(sv->up[k]);
-      }
-      if (sv->host[k]) (void)hipHostFree(sv->host[k]);
-    }
+    for (auto& kv : sv->slots) delete kv.second;
   }
   delete sv;
   return MSGPM_OK;
 }
 
 msgpm_status msgpm_server_scratch_bytes(int max_active, uint64_t* bytes) {
-  if (!bytes || max_active < 1) return fail(MSGPM_E_INVALID, "bad arguments");
-  *bytes = server_scratch(max_active);
+  if (!bytes || max_active < 1 || max_active > 4096) return fail(MSGPM_E_INVALID, "bad arguments");
+  *bytes = kCohorts * region_bytes(max_active);
   return MSGPM_OK;
 }
 
@@ -1054,6 +1260,12 @@ msgpm_status msgpm_server_submit(msgpm_server* sv, const msgpm_params* p, const 
       !d_occ1) {
     delete q;
     return fail(MSGPM_E_INVALID, "NULL or misaligned buffer");
+  }
+  const size_t steps = batch_schedule(q->P).size();
+  if (steps > (size_t)kMaxLaunches) {
+    delete q;
+    return fail(MSGPM_E_UNSUPPORTED, "a served pipeline has at most %d launches (these parameters give %zu)",
+                kMaxLaunches, steps);
   }
   std::lock_guard<std::mutex> lk(sv->mu);
   if (!sv->shape_set) {
@@ -1086,7 +1298,6 @@ msgpm_status msgpm_server_submit(msgpm_server* sv, const msgpm_params* p, const 
   q->desc.flow[1] = d_flow1;
   q->desc.occ[0] = d_occ0;
   q->desc.occ[1] = d_occ1;
-  q->steps = batch_schedule(q->P);
   q->ticket = sv->next_ticket++;
   sv->queue.push_back(q);
   sv->slots[q->ticket] = q;
@@ -1098,126 +1309,67 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   if (!sv || !d_scratch || (reinterpret_cast<uintptr_t>(d_scratch) & 255))
     return fail(MSGPM_E_INVALID, "server NULL or scratch NULL / misaligned");
   std::lock_guard<std::mutex> lk(sv->mu);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  msgpm_status st;
+  msgpm_status st = MSGPM_OK;
   server_retire(sv);
-  // cancelled in-flight pairs leave the round; their budget returns once the
-  // work already enqueued for them has passed
-  {
-    size_t ncancel = 0;
-    for (Slot* q : sv->active) ncancel += q->cancelled ? 1 : 0;
-    if ((st = reserve_events(sv, ncancel)) != MSGPM_OK) return st;
-    std::vector<Slot*> keep;
-    for (Slot* q : sv->active) {
-      if (!q->cancelled) {
-        keep.push_back(q);
-        continue;
-      }
-      q->done = sv->events.back();
-      sv->events.pop_back();
-      if ((st = check(hipEventRecord(q->done, s), "event")) != MSGPM_OK) return st;
-      q->state = 2;
-    }
-    sv->active.swap(keep);
+  if (pending) *pending = (int)sv->queue.size() + sv->in_flight;
+  if (sv->queue.empty()) return MSGPM_OK;
+  int ci = -1;
+  for (int k = 0; k < kCohorts && ci < 0; ++k) {
+    const int c = (sv->next + k) % kCohorts;
+    if (!sv->cohorts[c].busy) ci = c;
   }
-  // admission: first come, first served, while the budget and the slot count allow
-  while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
-         sv->in_use + sv->queue.front()->bytes <= sv->budget) {
-    Slot* q = sv->queue.front();
-    sv->queue.pop_front();
+  if (ci < 0) return MSGPM_OK;  // every region in use: admitted at a later step
+  // the cohort: queued pairs with the head's schedule, first come first served,
+  // while the budget and the in-flight limit allow
+  std::vector<Slot*> take;
+  uint64_t bytes = 0;
+  const DevParams head = sv->queue.front()->P;
+  for (Slot* q : sv->queue) {
+    if (!same_schedule(head, q->P)) continue;
+    if (sv->in_flight + (int)take.size() >= sv->max_active || sv->in_use + bytes + q->bytes > sv->budget) break;
+    take.push_back(q);
+    bytes += q->bytes;
+  }
+  if (take.empty()) return MSGPM_OK;
+  Cohort& c = sv->cohorts[ci];
+  if ((st = cohort_objects(sv, c)) != MSGPM_OK) return st;
+  const msgpm_tuning t = tune_for(head.r, head.C, head.fp16);
+  const int n = (int)take.size();
+  std::vector<DevParams> P(n);
+  std::vector<PairDesc> desc(n);
+  for (int i = 0; i < n; ++i) {
+    P[i] = take[i]->P;
+    desc[i] = take[i]->desc;
+  }
+  const Plan plan = make_plan(n, P, t, device_cus());
+  if ((int)plan.lists.size() > kMaxLists || plan.bytes > region_bytes(sv->max_active))
+    return fail(MSGPM_E_UNSUPPORTED, "cohort table of %llu bytes does not fit its region",
+                (unsigned long long)plan.bytes);
+  write_tables(plan, desc.data(), static_cast<char*>(c.host));
+  uint8_t* dev = static_cast<uint8_t*>(d_scratch) + (uint64_t)ci * region_bytes(sv->max_active);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // ordered after the caller's work so far (its frames), then on its own stream
+  if ((st = check(hipEventRecord(c.fork, s), "fork")) != MSGPM_OK) return st;
+  if ((st = check(hipStreamWaitEvent(c.s, c.fork, 0), "fork")) != MSGPM_OK) return st;
+  if ((st = check(hipMemcpyAsync(dev, c.host, plan.bytes, hipMemcpyHostToDevice, c.s), "upload")) != MSGPM_OK)
+    return st;
+  if ((st = run_plan_graph(plan, P[0], dev, c.s)) != MSGPM_OK) return st;
+  if ((st = check(hipEventRecord(c.done, c.s), "event")) != MSGPM_OK) return st;
+  for (Slot* q : take) {
     q->state = 1;
-    sv->in_use += q->bytes;
-    sv->active.push_back(q);
-  }
-  const int n = (int)sv->active.size();
-  if (pending) *pending = n + (int)sv->queue.size();
-  if (n == 0) return MSGPM_OK;
-  {
-    // completion events of the pairs whose last step this round launches
-    size_t nlast = 0;
-    for (Slot* q : sv->active) nlast += q->cursor + 1 == q->steps.size() ? 1 : 0;
-    if ((st = reserve_events(sv, nlast)) != MSGPM_OK) return st;
-  }
-  // group the active pairs by the kind of their next step; one launch per kind
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return sv->active[a]->steps[sv->active[a]->cursor].kind < sv->active[b]->steps[sv->active[b]->cursor].kind;
-  });
-  const uint64_t desc_bytes = align256((uint64_t)n * sizeof(PairDesc));
-  const uint64_t bytes = desc_bytes + (uint64_t)n * sizeof(Item);
-  struct Group {
-    int kind, first, count, total;
-    size_t lds;
-  };
-  std::vector<Group> groups;
-  std::vector<Item> items(n);
-  for (int k = 0; k < n;) {
-    const int kind = sv->active[order[k]]->steps[sv->active[order[k]]->cursor].kind;
-    Group gr{kind, k, 0, 0, 0};
-    int start = 0;
-    for (; k < n && sv->active[order[k]]->steps[sv->active[order[k]]->cursor].kind == kind; ++k) {
-      Slot* q = sv->active[order[k]];
-      const BatchStep& bs = q->steps[q->cursor];
-      Item& it = items[k];
-      memset(&it, 0, sizeof it);
-      it.pair = order[k];
-      it.nb = batch_blocks(kind, q->P, bs.a);
-      it.start = kind == BK_ZERO_ACTIVE ? gr.count : start;
-      for (int a = 0; a < 5; ++a) it.a[a] = bs.a[a];
-      start += (it.nb + kXcds - 1) / kXcds * kXcds;
-      if (kind == BK_RANSAC) {
-        const size_t m = ransac_smem_bytes(q->P, bs.a[0]);
-        gr.lds = m > gr.lds ? m : gr.lds;
+    q->cohort = ci;
+    c.pairs.push_back(q);
+    for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+      if (*it == q) {
+        sv->queue.erase(it);
+        break;
       }
-      ++gr.count;
-    }
-    gr.total = kind == BK_ZERO_ACTIVE ? gr.count : start;
-    groups.push_back(gr);
   }
-  // upload through the staging ring (the slot's previous upload has completed)
-  const int r = sv->ring;
-  sv->ring ^= 1;
-  if (sv->up[r] && (st = check(hipEventSynchronize(sv->up[r]), "staging")) != MSGPM_OK) return st;
-  if (sv->cap[r] < bytes) {
-    if (sv->host[r]) (void)hipHostFree(sv->host[r]);
-    sv->host[r] = nullptr;
-    sv->cap[r] = 0;
-    const size_t want = server_scratch(sv->max_active);
-    if ((st = check(host_alloc(&sv->host[r], want), "staging")) != MSGPM_OK) return st;
-    sv->cap[r] = want;
-  }
-  if (!sv->up[r] && (st = check(event_create(&sv->up[r]), "staging")) != MSGPM_OK) return st;
-  char* h = static_cast<char*>(sv->host[r]);
-  for (int i = 0; i < n; ++i) memcpy(h + (size_t)i * sizeof(PairDesc), &sv->active[i]->desc, sizeof(PairDesc));
-  memcpy(h + desc_bytes, items.data(), (size_t)n * sizeof(Item));
-  char* dev = static_cast<char*>(d_scratch);
-  if ((st = check(hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, s), "upload")) != MSGPM_OK) return st;
-  if ((st = check(hipEventRecord(sv->up[r], s), "staging")) != MSGPM_OK) return st;
-  const PairDesc* pd = reinterpret_cast<const PairDesc*>(dev);
-  const Item* it = reinterpret_cast<const Item*>(dev + desc_bytes);
-  DevParams P0 = sv->active[0]->P;
-  auto launch_group = [&](const Group& gr, hipStream_t q) {
-    const BatchStep& bs = sv->active[order[gr.first]]->steps[sv->active[order[gr.first]]->cursor];
-    return check(timed(bs.timer, q, [&] { return launch_batched(gr.kind, P0, pd, it + gr.first, gr.count, gr.total, gr.lds, q); }),
-                 "batched launch");
-  };
-  for (const Group& gr : groups)
-    if ((st = launch_group(gr, s)) != MSGPM_OK) return st;
-  // advance; pairs whose last step was launched get their completion event
-  std::vector<Slot*> still;
-  for (Slot* q : sv->active) {
-    if (++q->cursor < q->steps.size()) {
-      still.push_back(q);
-      continue;
-    }
-    q->done = sv->events.back();  // reserved above
-    sv->events.pop_back();
-    if ((st = check(hipEventRecord(q->done, s), "event")) != MSGPM_OK) return st;
-    q->state = 2;
-  }
-  sv->active.swap(still);
-  if (pending) *pending = (int)(sv->active.size() + sv->queue.size());
+  c.busy = true;
+  sv->in_use += bytes;
+  sv->in_flight += n;
+  sv->next = (ci + 1) % kCohorts;
+  if (pending) *pending = (int)sv->queue.size() + sv->in_flight;
   return MSGPM_OK;
 }
 
@@ -1234,8 +1386,7 @@ msgpm_status msgpm_server_cancel(msgpm_server* sv, uint64_t ticket, int* retired
         sv->queue.erase(it);
         break;
       }
-    sv->slots.erase(f);
-    delete q;
+    server_forget(sv, f);
     if (retired) *retired = 1;
   } else if (q->state == 1) {
     q->cancelled = true;
@@ -1258,17 +1409,9 @@ msgpm_status msgpm_server_wait(msgpm_server* sv, uint64_t ticket, int64_t timeou
       std::lock_guard<std::mutex> lk(sv->mu);
       auto f = sv->slots.find(ticket);
       if (f == sv->slots.end()) return fail(MSGPM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-      Slot* q = f->second;
-      if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
-        q->state = 3;
-        sv->in_use -= q->bytes;
-      }
-      if (q->state == 3) {
-        const bool cancelled = q->cancelled;
-        sv->events.push_back(q->done);
-        sv->slots.erase(f);
-        delete q;
-        if (cancelled) return fail(MSGPM_E_CANCELLED, "ticket %llu was cancelled", (unsigned long long)ticket);
+      if (f->second->state == 1) server_retire(sv);
+      if (f->second->state == 3) {
+        if (server_forget(sv, f)) return fail(MSGPM_E_CANCELLED, "ticket %llu was cancelled", (unsigned long long)ticket);
         return MSGPM_OK;
       }
     }
@@ -1293,17 +1436,9 @@ msgpm_status msgpm_server_poll(msgpm_server* sv, uint64_t ticket, int* done) {
   std::lock_guard<std::mutex> lk(sv->mu);
   auto f = sv->slots.find(ticket);
   if (f == sv->slots.end()) return fail(MSGPM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-  Slot* q = f->second;
-  if (q->state == 2 && hipEventQuery(q->done) == hipSuccess) {
-    q->state = 3;
-    sv->in_use -= q->bytes;
-  }
-  *done = q->state == 3;
-  if (*done) {
-    sv->events.push_back(q->done);
-    sv->slots.erase(f);
-    delete q;
-  }
+  if (f->second->state == 1) server_retire(sv);
+  *done = f->second->state == 3;
+  if (*done) server_forget(sv, f);
   return MSGPM_OK;
 }
 

@@ -155,42 +155,50 @@ __global__ __launch_bounds__(kBlock) void k_features(DevParams P, Ws w, const fl
 }
 
 // batched: grid.y = frame
-__global__ __launch_bounds__(kBlock) void kb_heq_clear(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                      int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  heq_clear_body(pd[it[i].pair].w);
+__global__ __launch_bounds__(kBlock) void kb_heq_clear(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    heq_clear_body(pd[it[i].pair].w);
+  });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_heq_hist(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                     int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  heq_hist_body(D.rgb[bk.y], D.P.W * D.P.H, D.w.heq + 256 * bk.y, bk);
+__global__ __launch_bounds__(kBlock) void kb_heq_hist(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<true>(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    heq_hist_body(D.rgb[bk.y], D.P.W * D.P.H, D.w.heq + 256 * bk.y, bk);
+  });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_heq_map(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                    int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  const int f = bk.y;
-  heq_map_body(D.w.heq + 256 * f, reinterpret_cast<float*>(D.w.heq + 512) + 256 * f,
-               reinterpret_cast<int*>(D.w.heq + 1024 + f), (unsigned)(D.P.W * D.P.H));
+__global__ __launch_bounds__(kBlock) void kb_heq_map(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<true>(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    const int f = bk.y;
+    heq_map_body(D.w.heq + 256 * f, reinterpret_cast<float*>(D.w.heq + 512) + 256 * f,
+                 reinterpret_cast<int*>(D.w.heq + 1024 + f), (unsigned)(D.P.W * D.P.H));
+  });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_features(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                     int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  features_body(D.rgb[bk.y], D.P.W, D.P.H, D.P.C, D.P.fp16, heq_map(D.P, D.w, bk.y), heq_flat(D.P, D.w, bk.y),
-                const_cast<void*>(D.w.feat[bk.y]), bk);
+__global__ __launch_bounds__(kBlock) void kb_features(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    features_body(D.rgb[bk.y], D.P.W, D.P.H, D.P.C, D.P.fp16, heq_map(D.P, D.w, bk.y), heq_flat(D.P, D.w, bk.y),
+                  const_cast<void*>(D.w.feat[bk.y]), bk);
+  });
 }
 
 int heq_hist_blocks(const DevParams& P) { return (P.W * P.H + kHeqSpan - 1) / kHeqSpan; }
@@ -243,13 +251,15 @@ __global__ __launch_bounds__(kBlock) void k_init_pixels(DevParams P, Ws w, const
   init_pixels_body(P, w, init0, init1, blk_here());
 }
 
-__global__ __launch_bounds__(kBlock) void kb_init_pixels(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                        int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  init_pixels_body(D.P, D.w, D.init[0], D.init[1], bk);
+__global__ __launch_bounds__(kBlock) void kb_init_pixels(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    init_pixels_body(D.P, D.w, D.init[0], D.init[1], bk);
+  });
 }
 
 __device__ __forceinline__ void init_planes_body(const DevParams& P, const Ws& w, Blk bk) {
@@ -284,13 +294,15 @@ __device__ __forceinline__ void init_planes_body(const DevParams& P, const Ws& w
 
 __global__ __launch_bounds__(kBlock) void k_init_planes(DevParams P, Ws w) { init_planes_body(P, w, blk_here()); }
 
-__global__ __launch_bounds__(kBlock) void kb_init_planes(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                        int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  init_planes_body(D.P, D.w, bk);
+__global__ __launch_bounds__(kBlock) void kb_init_planes(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    init_planes_body(D.P, D.w, bk);
+  });
 }
 
 hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* init0, const int32_t* init1,
@@ -305,25 +317,25 @@ hipError_t launch_init_state(const DevParams& P, const Ws& w, const int32_t* ini
   return hipGetLastError();
 }
 
-hipError_t launch_batched_init(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s) {
+hipError_t launch_batched_init(int kind, const uint8_t* tab, int k, int grid, BArgs A, hipStream_t s) {
   switch (kind) {
     case BK_HEQ_CLEAR:
-      hipLaunchKernelGGL(kb_heq_clear, dim3(total, 1), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_heq_clear, dim3(grid, 1), dim3(kBlock), 0, s, tab, k, A);
       break;
     case BK_HEQ_HIST:
-      hipLaunchKernelGGL(kb_heq_hist, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_heq_hist, dim3(grid, 2), dim3(kBlock), 0, s, tab, k, A);
       break;
     case BK_HEQ_MAP:
-      hipLaunchKernelGGL(kb_heq_map, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_heq_map, dim3(grid, 2), dim3(kBlock), 0, s, tab, k, A);
       break;
     case BK_FEATURES:
-      hipLaunchKernelGGL(kb_features, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_features, dim3(grid, 2), dim3(kBlock), 0, s, tab, k, A);
       break;
     case BK_INIT_PIXELS:
-      hipLaunchKernelGGL(kb_init_pixels, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_init_pixels, dim3(grid, 2), dim3(kBlock), 0, s, tab, k, A);
       break;
     case BK_INIT_PLANES:
-      hipLaunchKernelGGL(kb_init_planes, dim3(total, 1), dim3(kBlock), 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_init_planes, dim3(grid, 1), dim3(kBlock), 0, s, tab, k, A);
       break;
     default:
       return hipErrorInvalidValue;

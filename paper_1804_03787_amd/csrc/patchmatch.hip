@@ -425,13 +425,15 @@ __global__ __launch_bounds__(kBlock) void k_eval_cost(DevParams P, Ws w, int mod
   eval_cost_body<R, C, FP16, IDENT>(P, w, blk_here(), mode);
 }
 
-template <int R, int C, bool FP16, bool IDENT>
-__global__ __launch_bounds__(kBlock) void kb_eval_cost(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                      int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  eval_cost_body<R, C, FP16, IDENT>(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+template <int R, int C, bool FP16, bool IDENT, bool LOOP>
+__global__ __launch_bounds__(kBlock) void kb_eval_cost(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<false, LOOP>(it, n, total, [&](int i, Blk bk) {
+    eval_cost_body<R, C, FP16, IDENT>(pd[it[i].pair].P, pd[it[i].pair].w, bk, A.a[0]);
+  });
 }
 
 // Candidate loops of one pixel: the four neighbours' offsets (left, right, up,
@@ -706,9 +708,11 @@ __global__ void k_zero_active(Ws w) {
   if (threadIdx.x < 8) w.act_count[threadIdx.x] = 0u;
 }
 
-// batched: one workgroup per item
-__global__ void kb_zero_active(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  if (threadIdx.x < 8 && (int)blockIdx.x < n) pd[it[blockIdx.x].pair].w.act_count[threadIdx.x] = 0u;
+// batched: each workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ void kb_zero_active(const uint8_t* __restrict__ tab, int k) {
+  const BatchView V = batch_view(tab, k);
+  for (int i = blockIdx.x; i < V.n; i += gridDim.x)
+    if (threadIdx.x < 8) V.pd[V.it[i].pair].w.act_count[threadIdx.x] = 0u;
 }
 
 constexpr int kListSpan = 4;  // pixels of the colour per thread of k_active_list
@@ -773,12 +777,14 @@ __global__ __launch_bounds__(kBlock) void k_active_list(DevParams P, Ws w, int c
   active_list_body(P, w, blk_here(), colour);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_active_list(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                        int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  active_list_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+__global__ __launch_bounds__(kBlock) void kb_active_list(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<true>(it, n, total, [&](int i, Blk bk) {
+    active_list_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, A.a[0]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -896,14 +902,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 
   pm_halfsweep_body<R, C, FP16, IDENT>(P, w, blk_here(), colour, iter, slot, mode);
 }
 
-template <int R, int C, bool FP16, bool IDENT>
+template <int R, int C, bool FP16, bool IDENT, bool LOOP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(IDENT ? 4 : 3))) void kb_pm_halfsweep(
-    const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  pm_halfsweep_body<R, C, FP16, IDENT>(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1], I.a[2], I.a[3]);
+    const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<false, LOOP>(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    pm_halfsweep_body<R, C, FP16, IDENT>(pd[I.pair].P, pd[I.pair].w, bk, A.a[0], A.a[1], A.a[2], A.a[3]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,41 +1011,52 @@ hipError_t launch_eval_cost(const DevParams& P, const Ws& w, int mode, hipStream
   MSGPM_DISPATCH(dispatch_ec, P, w, mode, s);
 }
 
-template <int R, int C, bool FP16>
-static hipError_t dispatch_batched(int kind, const PairDesc* pd, const Item* it, int n, int total, hipStream_t s) {
-  const dim3 grid(total, 2), block(kBlock);
+template <int R, int C, bool FP16, bool LOOP>
+static void dispatch_batched_form(int kind, const uint8_t* tab, int k, dim3 grid, BArgs A, hipStream_t s) {
+  const dim3 block(kBlock);
   switch (kind) {
     case BK_PM_INIT:
     case BK_PM_RESTRICTED_IDENT:
-      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, true>), grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, true, LOOP>), grid, block, 0, s, tab, k, A);
       break;
     case BK_PM_RESTRICTED:
-      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, false>), grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL((kb_pm_halfsweep<R, C, FP16, false, LOOP>), grid, block, 0, s, tab, k, A);
       break;
     case BK_EVAL_COST_IDENT:
-      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, true>), grid, block, 0, s, pd, it, n);
-      break;
-    case BK_EVAL_COST_PLANE:
-      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, false>), grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, true, LOOP>), grid, block, 0, s, tab, k, A);
       break;
     default:
-      return hipErrorInvalidValue;
+      hipLaunchKernelGGL((kb_eval_cost<R, C, FP16, false, LOOP>), grid, block, 0, s, tab, k, A);
+      break;
   }
+}
+
+// persistent (loop over the virtual workgroups) or one-shot (grid >= total)
+template <int R, int C, bool FP16>
+static hipError_t dispatch_batched(int kind, const uint8_t* tab, int k, int ngrid, BArgs A, bool persist,
+                                   hipStream_t s) {
+  if (kind != BK_PM_INIT && kind != BK_PM_RESTRICTED_IDENT && kind != BK_PM_RESTRICTED &&
+      kind != BK_EVAL_COST_IDENT && kind != BK_EVAL_COST_PLANE)
+    return hipErrorInvalidValue;
+  if (persist)
+    dispatch_batched_form<R, C, FP16, true>(kind, tab, k, dim3(ngrid, 2), A, s);
+  else
+    dispatch_batched_form<R, C, FP16, false>(kind, tab, k, dim3(ngrid, 2), A, s);
   return hipGetLastError();
 }
 
-hipError_t launch_batched_pm(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
-                             hipStream_t s) {
+hipError_t launch_batched_pm(int kind, const DevParams& P0, const uint8_t* tab, int k, int grid, BArgs A,
+                             bool persist, hipStream_t s) {
   if (kind == BK_ZERO_ACTIVE) {
-    hipLaunchKernelGGL(kb_zero_active, dim3(n), dim3(kWave), 0, s, pd, it, n);
+    hipLaunchKernelGGL(kb_zero_active, dim3(grid), dim3(kWave), 0, s, tab, k);
     return hipGetLastError();
   }
   if (kind == BK_ACTIVE_LIST) {
-    hipLaunchKernelGGL(kb_active_list, dim3(total, 2), dim3(kBlock), 0, s, pd, it, n);
+    hipLaunchKernelGGL(kb_active_list, dim3(grid, 2), dim3(kBlock), 0, s, tab, k, A);
     return hipGetLastError();
   }
   const DevParams& P = P0;
-  MSGPM_DISPATCH(dispatch_batched, kind, pd, it, n, total, s);
+  MSGPM_DISPATCH(dispatch_batched, kind, tab, k, grid, A, persist, s);
 }
 
 // Workgroups of the PatchMatch-side kernels for one pair (the single-pair

@@ -834,13 +834,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 }
 
 template <int UMAX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_ransac(const PairDesc* __restrict__ pd,
-                                                                                          const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  ransac_body<UMAX>(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_ransac(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<true>(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    ransac_body<UMAX>(pd[I.pair].P, pd[I.pair].w, bk, A.a[0], A.a[1]);
+  });
 }
 
 // Windows of more than this many points take the 8-points-per-lane scoring.
@@ -902,12 +904,15 @@ __global__ __launch_bounds__(kBlock) void k_assign(DevParams P, Ws w, int level,
   assign_body(P, w, blk_here(), level, stage, tentative);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_assign(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  assign_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1], I.a[2]);
+__global__ __launch_bounds__(kBlock) void kb_assign(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    assign_body(pd[I.pair].P, pd[I.pair].w, bk, A.a[0], A.a[1], A.a[2]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -970,12 +975,15 @@ __global__ __launch_bounds__(kBlock) void k_symmetry(DevParams P, Ws w, int leve
   symmetry_body(P, w, blk_here(), level, stage);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_symmetry(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  symmetry_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0], I.a[1]);
+__global__ __launch_bounds__(kBlock) void kb_symmetry(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item<true>(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    symmetry_body(pd[I.pair].P, pd[I.pair].w, bk, A.a[0], A.a[1]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -999,12 +1007,15 @@ __global__ __launch_bounds__(kBlock) void k_fb(DevParams P, Ws w) {
   fb_body(P, w, blk_here());
 }
 
-__global__ __launch_bounds__(kBlock) void kb_fb(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  fb_body(pd[I.pair].P, pd[I.pair].w, bk);
+__global__ __launch_bounds__(kBlock) void kb_fb(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    fb_body(pd[I.pair].P, pd[I.pair].w, bk);
+  });
 }
 
 __device__ __forceinline__ void commit_body(const DevParams& P, const Ws& w, Blk bk) {
@@ -1018,12 +1029,15 @@ __global__ __launch_bounds__(kBlock) void k_commit(DevParams P, Ws w) {
   commit_body(P, w, blk_here());
 }
 
-__global__ __launch_bounds__(kBlock) void kb_commit(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  commit_body(pd[I.pair].P, pd[I.pair].w, bk);
+__global__ __launch_bounds__(kBlock) void kb_commit(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    commit_body(pd[I.pair].P, pd[I.pair].w, bk);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,11 +1088,14 @@ __device__ __forceinline__ void uq_body(const DevParams& P, const Ws& w, Blk bk,
 
 __global__ __launch_bounds__(kBlock) void k_unique(DevParams P, Ws w, int phase) { uq_body(P, w, blk_here(), phase); }
 
-__global__ __launch_bounds__(kBlock) void kb_unique(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  uq_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+__global__ __launch_bounds__(kBlock) void kb_unique(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    uq_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, A.a[0]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,19 +1151,24 @@ __device__ __forceinline__ void fill_body(const DevParams& P, const Ws& w, Blk b
 __global__ __launch_bounds__(kBlock) void k_fill_clear(Ws w) { fill_clear_body(w); }
 __global__ __launch_bounds__(kBlock) void k_fill(DevParams P, Ws w, int t) { fill_body(P, w, blk_here(), t); }
 
-__global__ __launch_bounds__(kBlock) void kb_fill_clear(const PairDesc* __restrict__ pd, const Item* __restrict__ it,
-                                                       int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  fill_clear_body(pd[it[i].pair].w);
+__global__ __launch_bounds__(kBlock) void kb_fill_clear(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    fill_clear_body(pd[it[i].pair].w);
+  });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_fill(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  fill_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, it[i].a[0]);
+__global__ __launch_bounds__(kBlock) void kb_fill(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    fill_body(pd[it[i].pair].P, pd[it[i].pair].w, bk, A.a[0]);
+  });
 }
 
 __device__ __forceinline__ void nnf_update_body(const DevParams& P, const Ws& w, Blk bk, int level) {
@@ -1187,12 +1209,15 @@ __global__ __launch_bounds__(kBlock) void k_nnf_update(DevParams P, Ws w, int le
   nnf_update_body(P, w, blk_here(), level);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_nnf_update(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const Item& I = it[i];
-  nnf_update_body(pd[I.pair].P, pd[I.pair].w, bk, I.a[0]);
+__global__ __launch_bounds__(kBlock) void kb_nnf_update(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const Item& I = it[i];
+    nnf_update_body(pd[I.pair].P, pd[I.pair].w, bk, A.a[0]);
+  });
 }
 
 __device__ __forceinline__ void finalize_body(const DevParams& P, const Ws& w, Blk bk, float* flow0, float* flow1,
@@ -1227,12 +1252,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(DevParams P, Ws w, float* f
   finalize_body(P, w, blk_here(), flow0, flow1, occ0, occ1);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_finalize(const PairDesc* __restrict__ pd, const Item* __restrict__ it, int n) {
-  int i;
-  Blk bk;
-  if (!batch_blk(it, n, i, bk)) return;
-  const PairDesc& D = pd[it[i].pair];
-  finalize_body(D.P, D.w, bk, D.flow[0], D.flow[1], D.occ[0], D.occ[1]);
+__global__ __launch_bounds__(kBlock) void kb_finalize(const uint8_t* __restrict__ tab, int k, BArgs A) {
+  const BatchView V = batch_view(tab, k);
+  const PairDesc* __restrict__ pd = V.pd;
+  const Item* __restrict__ it = V.it;
+  const int n = V.n, total = V.total;
+  for_each_item(it, n, total, [&](int i, Blk bk) {
+    const PairDesc& D = pd[it[i].pair];
+    finalize_body(D.P, D.w, bk, D.flow[0], D.flow[1], D.occ[0], D.occ[1]);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1249,6 +1277,8 @@ size_t ransac_smem_bytes(const DevParams& P, int level) {
   const size_t n = (size_t)bw * bh;
   return kAuxDoubles * sizeof(double) + 2 * n * sizeof(uint32_t);
 }
+
+size_t ransac_smem_bytes_window(int B) { return kAuxDoubles * sizeof(double) + 2 * (size_t)B * B * sizeof(uint32_t); }
 
 hipError_t launch_ransac(const DevParams& P, const Ws& w, int level, int stage, hipStream_t s) {
   const size_t sm = ransac_smem_bytes(P, level);
@@ -1312,47 +1342,47 @@ hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float*
   return hipGetLastError();
 }
 
-hipError_t launch_batched_planes(int kind, const PairDesc* pd, const Item* it, int n, int total, size_t lds,
+hipError_t launch_batched_planes(int kind, const uint8_t* tab, int k, int ngrid, size_t lds, BArgs A,
                                  hipStream_t s) {
-  const dim3 grid(total, batch_grid_y(kind)), block(kBlock);
+  const dim3 grid(ngrid, batch_grid_y(kind)), block(kBlock);
   switch (kind) {
     case BK_RANSAC: {
       hipError_t e;
       if (ransac_points(lds) > kRansacWide) {
         if ((e = ransac_lds(&kb_ransac<8>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(kb_ransac<8>, grid, block, lds, s, pd, it, n);
+        hipLaunchKernelGGL(kb_ransac<8>, grid, block, lds, s, tab, k, A);
       } else {
         if ((e = ransac_lds(&kb_ransac<4>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(kb_ransac<4>, grid, block, lds, s, pd, it, n);
+        hipLaunchKernelGGL(kb_ransac<4>, grid, block, lds, s, tab, k, A);
       }
       break;
     }
     case BK_ASSIGN:
-      hipLaunchKernelGGL(kb_assign, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_assign, grid, block, 0, s, tab, k, A);
       break;
     case BK_SYMMETRY:
-      hipLaunchKernelGGL(kb_symmetry, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_symmetry, grid, block, 0, s, tab, k, A);
       break;
     case BK_FB:
-      hipLaunchKernelGGL(kb_fb, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_fb, grid, block, 0, s, tab, k, A);
       break;
     case BK_COMMIT:
-      hipLaunchKernelGGL(kb_commit, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_commit, grid, block, 0, s, tab, k, A);
       break;
     case BK_NNF_UPDATE:
-      hipLaunchKernelGGL(kb_nnf_update, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_nnf_update, grid, block, 0, s, tab, k, A);
       break;
     case BK_FINALIZE:
-      hipLaunchKernelGGL(kb_finalize, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_finalize, grid, block, 0, s, tab, k, A);
       break;
     case BK_UNIQUE:
-      hipLaunchKernelGGL(kb_unique, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_unique, grid, block, 0, s, tab, k, A);
       break;
     case BK_FILL_CLEAR:
-      hipLaunchKernelGGL(kb_fill_clear, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_fill_clear, grid, block, 0, s, tab, k, A);
       break;
     case BK_FILL:
-      hipLaunchKernelGGL(kb_fill, grid, block, 0, s, pd, it, n);
+      hipLaunchKernelGGL(kb_fill, grid, block, 0, s, tab, k, A);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1398,8 +1428,8 @@ int batch_blocks(int kind, const DevParams& P, const int* a) {
   }
 }
 
-hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, const Item* it, int n, int total,
-                          size_t lds, hipStream_t s) {
+hipError_t launch_batched(int kind, const DevParams& P0, const uint8_t* tab, int k, int grid, size_t lds, BArgs A,
+                          bool persist, hipStream_t s) {
   switch (kind) {
     case BK_HEQ_CLEAR:
     case BK_HEQ_HIST:
@@ -1407,7 +1437,7 @@ hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, con
     case BK_FEATURES:
     case BK_INIT_PIXELS:
     case BK_INIT_PLANES:
-      return launch_batched_init(kind, pd, it, n, total, s);
+      return launch_batched_init(kind, tab, k, grid, A, s);
     case BK_EVAL_COST_IDENT:
     case BK_EVAL_COST_PLANE:
     case BK_ZERO_ACTIVE:
@@ -1415,9 +1445,9 @@ hipError_t launch_batched(int kind, const DevParams& P0, const PairDesc* pd, con
     case BK_PM_INIT:
     case BK_PM_RESTRICTED:
     case BK_PM_RESTRICTED_IDENT:
-      return launch_batched_pm(kind, P0, pd, it, n, total, s);
+      return launch_batched_pm(kind, P0, tab, k, grid, A, persist, s);
     default:
-      return launch_batched_planes(kind, pd, it, n, total, lds, s);
+      return launch_batched_planes(kind, tab, k, grid, lds, A, s);
   }
 }
 

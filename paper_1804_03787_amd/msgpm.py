@@ -102,6 +102,12 @@ def lib() -> ctypes.CDLL:
         L.msgpm_batch_query.restype = ctypes.c_int
         L.msgpm_solve_batch.argtypes = [i, P] + [vp] * 11
         L.msgpm_solve_batch.restype = ctypes.c_int
+        L.msgpm_solve_batch_graph.argtypes = [i, P] + [vp] * 11
+        L.msgpm_solve_batch_graph.restype = ctypes.c_int
+        L.msgpm_tuning_set.argtypes = [ctypes.POINTER(Tuning)]
+        L.msgpm_tuning_set.restype = ctypes.c_int
+        L.msgpm_tuning_get.argtypes = [ctypes.POINTER(Tuning)]
+        L.msgpm_tuning_get.restype = ctypes.c_int
         u64, pu64 = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)
         for name, args in {
             "msgpm_server_create": [u64, i, ctypes.POINTER(vp)],
@@ -125,6 +131,7 @@ def lib() -> ctypes.CDLL:
         L.msgpm_timing_read.restype = ctypes.c_int
         L.msgpm_last_error.restype = ctypes.c_char_p
         L.msgpm_last_error.argtypes = []
+        _install_tuning(L)
         _lib = L
     return _lib
 
@@ -137,6 +144,11 @@ def _call(name, *args):
 
 TIMER_KINDS = ["features", "init", "eval_cost", "pm_init", "pm_restricted", "ransac", "assign", "symmetry", "fb",
                "nnf_update", "finalize", "pm_list", "pm_restricted_ident", "fill"]
+
+
+def graph_cache_clear():
+    """Drops every cached HIP graph (msgpm_graph_cache_clear)."""
+    _call("msgpm_graph_cache_clear")
 
 
 def timing_enable(on: bool = True):
@@ -341,6 +353,55 @@ def solve_static(p: Params, rgb1, rgb2, flows, occs, planes=None, init0=None, in
           _ptr(flows[0]), _ptr(flows[1]), _ptr(occs[0]), _ptr(occs[1]), _ptr(planes), _stream())
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("patch_radius", ctypes.c_int32), ("channels", ctypes.c_int32), ("fp16", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32 * 4)]
+
+
+TUNE_CLASSES = ["pm_identity", "pm_distorted", "ransac", "pixel"]
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+
+
+def tuning_key(r: int, C: int, fp16: bool) -> str:
+    return f"r{r}_C{C}_{'fp16' if fp16 else 'fp32'}"
+
+
+def tuning_get(r: int = 0, C: int = 0, fp16=None) -> dict:
+    """Resident workgroups per compute unit of the persistent batched launches
+    that apply to instantiation (r, C, storage); 0 / 0 / None: the default."""
+    t = Tuning()
+    t.patch_radius, t.channels, t.fp16 = r, C, -1 if fp16 is None else int(fp16)
+    _call("msgpm_tuning_get", ctypes.byref(t))
+    return {k: int(t.wg_per_cu[i]) for i, k in enumerate(TUNE_CLASSES)}
+
+
+def tuning_set(r: int = 0, C: int = 0, fp16=None, **wg_per_cu):
+    """Stores a shape for instantiation (r, C, storage) (0 / 0 / None: the
+    default); classes not given keep the value that applied so far."""
+    cur = tuning_get(r, C, fp16)
+    cur.update(wg_per_cu)
+    t = Tuning()
+    t.patch_radius, t.channels, t.fp16 = r, C, -1 if fp16 is None else int(fp16)
+    for i, k in enumerate(TUNE_CLASSES):
+        t.wg_per_cu[i] = int(cur[k])
+    _call("msgpm_tuning_set", ctypes.byref(t))
+
+
+def _install_tuning(L):
+    """Installs the autotuner's stored choices (paper_1804_03787_amd/tuning.json,
+    written by autotune.py), one entry per instantiation."""
+    if not os.path.exists(TUNING_PATH):
+        return
+    import json
+    for key, entry in json.load(open(TUNING_PATH)).get("choices", {}).items():
+        t = Tuning()
+        t.patch_radius, t.channels, t.fp16 = entry["r"], entry["C"], int(entry["fp16"])
+        for i, k in enumerate(TUNE_CLASSES):
+            t.wg_per_cu[i] = int(entry["wg_per_cu"][k])
+        if L.msgpm_tuning_set(ctypes.byref(t)) != 0:
+            raise MsgpmError("msgpm_tuning_set", 1, f"{TUNING_PATH}: entry {key}")
+
+
 def debug_fail_allocations(n: int):
     """Test hook: the library's next n own allocations fail (E_OOM)."""
     _call("msgpm_debug_fail_allocations", int(n))
@@ -374,8 +435,9 @@ class Batch:
                       for q in self.pairs]
         self.occs = [[torch.empty((q.H, q.W), dtype=torch.uint8, device=dev) for _ in range(2)] for q in self.pairs]
 
-    def solve(self, frames1, frames2, inits=None):
-        """Returns per pair ([flow0, flow1], [occ0, occ1]) as device tensors."""
+    def solve(self, frames1, frames2, inits=None, graph=False):
+        """Returns per pair ([flow0, flow1], [occ0, occ1]) as device tensors.
+        graph: one HIP graph launch (msgpm_solve_batch_graph)."""
         n = len(self.pairs)
         a = [q._frame(f) for q, f in zip(self.pairs, frames1)]
         b = [q._frame(f) for q, f in zip(self.pairs, frames2)]
@@ -390,7 +452,7 @@ class Batch:
             i0, i1 = arr(t0), arr(t1)
             keep += [t0, t1]
         ws = arr([q.ws for q in self.pairs])
-        _call("msgpm_solve_batch", n, self.params, arr(a), arr(b), i0, i1, ws,
+        _call("msgpm_solve_batch_graph" if graph else "msgpm_solve_batch", n, self.params, arr(a), arr(b), i0, i1, ws,
               arr([f[0] for f in self.flows]), arr([f[1] for f in self.flows]),
               arr([o[0] for o in self.occs]), arr([o[1] for o in self.occs]), self.scratch_ptr, _stream())
         self._keep = keep
@@ -399,8 +461,9 @@ class Batch:
 
 class Server:
     """Continuous batching (msgpm_server_*): pairs submitted at any time are
-    admitted within an HBM budget and advanced one pipeline step per round,
-    pairs at the same kind of step sharing one launch."""
+    admitted within an HBM budget; each step admits the waiting pairs that fit
+    as one cohort, whose whole batched pipeline is enqueued as one graph
+    launch on one of the server's streams, beside the cohorts still running."""
 
     def __init__(self, hbm_budget: int, max_active: int, device="cuda"):
         self.device = torch.device(device)

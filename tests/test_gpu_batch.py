@@ -3,6 +3,8 @@ per phase, and each pair's outputs (flow, occlusion, plane table, NNF) are
 bit-identical to a msgpm_solve of that pair alone.  GPU against GPU: the
 single-pair path is held to the oracle by the parity tests, and one batch of
 FP16-storage pairs is also compared with the oracle directly."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -31,6 +33,9 @@ def _same(a, b):
 
 
 def _run(msgpm, pairs, params, inits=None):
+    """Each pair alone, then the batch three ways: eager launches, one graph
+    launch (twice: capture, then a replay), and eager with every persistent
+    launch at one resident workgroup per compute unit; all bit-identical."""
     alone = []
     for i, (pr, p) in enumerate(zip(pairs, params)):
         H, W = pr.shape
@@ -40,9 +45,20 @@ def _run(msgpm, pairs, params, inits=None):
         alone.append(_outputs(g, flows, occs))
     gs = [msgpm.Pair(pr.shape[1], pr.shape[0], **p) for pr, p in zip(pairs, params)]
     batch = msgpm.Batch(gs)
-    res = batch.solve([pr.frame1 for pr in pairs], [pr.frame2 for pr in pairs], inits)
-    for i, g in enumerate(gs):
-        _same(alone[i], _outputs(g, *res[i]))
+    f1, f2 = [pr.frame1 for pr in pairs], [pr.frame2 for pr in pairs]
+    key = dict(r=params[0]["r"], C=params[0]["C"], fp16=bool(params[0]["fp16"]))
+    saved = msgpm.tuning_get(**key)
+    try:
+        for graph, tune in ((False, None), (True, None), (True, None), (False, 1)):
+            if tune is not None:
+                msgpm.tuning_set(**key, **{k: tune for k in saved})
+            for g in gs:
+                g.ws.zero_()
+            res = batch.solve(f1, f2, inits, graph=graph)
+            for i, g in enumerate(gs):
+                _same(alone[i], _outputs(g, *res[i]))
+    finally:
+        msgpm.tuning_set(**key, **saved)
     return gs
 
 
@@ -67,6 +83,32 @@ def test_batch_paper_sizes_match_single_solves():
     full = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0)
     params = [_gpu_params(dict(full, seed=100 + i, fp16=True)) for i in range(len(sizes))]
     _run(msgpm, pairs, params)
+
+
+def test_batch_graph_serves_other_pairs_with_the_same_schedule():
+    """The batched graph depends on the schedule and the table address only: a
+    graph captured for one batch, replayed for a batch of other pairs (other
+    sizes and number) through the same table buffer, gives each pair's lone
+    result."""
+    msgpm = _need_gpu()
+    base = _gpu_params(TINY_PARAMS)
+    first = [(synth.tiny_pair(0), dict(base)), (synth.planar_pair(160, 120, seed=3, scale=0.15), dict(base, seed=5))]
+    second = [(synth.planar_pair(97, 61, seed=4, scale=0.1), dict(base, seed=6)),
+              (synth.planar_pair(200, 144, seed=7, scale=0.1), dict(base, seed=7)),
+              (synth.tiny_pair(0), dict(base, seed=8))]
+    batches = []
+    for scenes in (first, second):
+        gs = [msgpm.Pair(pr.shape[1], pr.shape[0], **p) for pr, p in scenes]
+        batches.append((scenes, gs, msgpm.Batch(gs)))
+    big = max(b.scratch.numel() for _, _, b in batches)
+    shared = torch.empty(big + 256, dtype=torch.uint8, device="cuda")
+    ptr = ctypes.c_void_p(shared.data_ptr() + (-shared.data_ptr()) % 256)
+    for scenes, gs, b in batches:
+        b.scratch, b.scratch_ptr = shared, ptr
+        res = b.solve([pr.frame1 for pr, _ in scenes], [pr.frame2 for pr, _ in scenes], graph=True)
+        for (pr, p), g, r in zip(scenes, gs, res):
+            alone = msgpm.Pair(pr.shape[1], pr.shape[0], **p)
+            _same(_outputs(alone, *alone.solve(pr.frame1, pr.frame2)), _outputs(g, *r))
 
 
 def test_batch_rejects_mixed_shapes():

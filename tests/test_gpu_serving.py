@@ -90,8 +90,9 @@ def test_serving_admission_by_budget_and_errors():
 
 def test_serving_cancel_queued_and_in_flight():
     """A queued pair cancelled before admission is gone at once; an in-flight
-    pair cancelled after a few rounds leaves the rounds, is reported done and
-    returns its budget; the pair left running still matches its lone solve."""
+    pair cancelled after its cohort was enqueued runs to its end, is reported
+    done and returns its budget; the pair left running still matches its lone
+    solve."""
     msgpm = _need_gpu()
     scenes = _scenes()[:3]
     alone = []
@@ -106,7 +107,7 @@ def test_serving_cancel_queued_and_in_flight():
         srv.poll(ts[2])
     for _ in range(5):
         srv.step()
-    assert not srv.cancel(ts[1])        # in flight: leaves at the next round
+    assert not srv.cancel(ts[1])        # in flight: its enqueued work completes
     done = {}
     for _ in range(100000):
         pend = srv.step()
@@ -171,13 +172,12 @@ def test_serving_wait_status_codes():
     srv = msgpm.Server(hbm_budget=1 << 34, max_active=4)
     keep = srv.submit(msgpm.Pair(W, H, **p), pr.frame1, pr.frame2)
     drop = srv.submit(msgpm.Pair(W, H, **dict(p, seed=3)), pr.frame1, pr.frame2)
-    for _ in range(5):
-        srv.step()
     with pytest.raises(msgpm.MsgpmError) as e:
-        srv.wait(keep, 1000)
+        srv.wait(keep, 1000)             # queued: not admitted before a step
     assert e.value.status == msgpm.E_TIMEOUT
     assert not srv.poll(keep)
-    assert not srv.cancel(drop)          # in flight: dropped at the next round
+    srv.step()                           # both admitted, their pipeline enqueued
+    assert not srv.cancel(drop)          # in flight: runs to its end, reported cancelled
     while srv.step():
         pass
     srv.wait(keep, 10_000_000)
