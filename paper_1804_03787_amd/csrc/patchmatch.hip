@@ -441,8 +441,9 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const uint8_t* __restrict
 // the best offset after those; a candidate replaces the best only if strictly
 // better.  Two schedules with identical decisions:
 //  * identity patches (short per-candidate chain): candidates in batches of
-//    NB whose gathers are issued together, compared in candidate order after
-//    the batch, with an exact early rejection taken by the whole wave;
+//    NB; the first third of the rows of the batch is gathered together, then
+//    each candidate still in the running is finished on its own, with exact
+//    early rejections per lane group (FP32 records);
 //  * distorted patches (long chain, register-heavy): one candidate at a time
 //    with the exact early rejection of group_cost.
 
@@ -450,6 +451,12 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const uint8_t* __restrict
 // or three rows per chunk take the kernel to 256 VGPRs and lose more than the
 // longer chunks gain).
 constexpr int kIdentRows = 1;
+// Rows per step when one identity-patch candidate is finished (FP32 records),
+// with an early-rejection check before each step.  Measured on MI355X at
+// 1024x436 (whole pipeline, r = 4): checks at rows 3 and 6 take 33.1 ms per
+// pair, a check at row 3 only 33.9 ms, checks at rows 3, 5 and 7 33.8 ms,
+// one at every row 38.2 ms; the batch-wide check this replaced took 37.3 ms.
+constexpr int kIdentStep = 3;
 
 // Rows [T0, T) of NB identity-patch targets added to acc, in chunks of
 // kIdentRows: each lane walks its column once, and the loads of a chunk (all
@@ -481,40 +488,60 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
   }
 }
 
-// Group costs of NB identity-patch targets, every candidate summed in the same
-// order as a lone evaluation.  FP32 records: after the first third of the
-// rows, if no candidate the batch evaluates, in any group of the wave, has a
-// partial sum below `bound` (the best cost when the batch starts), none can be
-// strictly better: taps are non-negative and FP32 addition is monotone, so the
-// full sums are at least the partial ones.  The wave then skips the other rows
-// (returns false; costs are not set).  The decision is taken per wave because
-// skipping rows of single candidates takes branches inside the load chunk that
-// make the compiler spill (measured on MI355X: 1 % faster per pair; a second
-// check at two thirds of the rows adds spills and gains nothing measurable).
-// FP16 records need half the load instructions, and there the extra partial
-// sums cost more than the rows they save (8 % slower per pair), so those
-// batches are always summed to the end.
-template <int R, int C, bool FP16, int NB>
-__device__ inline bool group_cost_ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
-                                              const int* ty, const bool* ok, float bound, float gw, int base,
-                                              float* cost) {
-  constexpr int T = 2 * R + 1, TE = T / 3;
-  float acc[NB];
+// Rows [T0, T) of one identity-patch target added to acc: the loads of all
+// rows are issued ahead of their arithmetic.
+template <int R, int C, bool FP16, int T0, int T>
+__device__ inline float ident_rows1(float acc, const LaneCol<R, C, true>& L, Feat F2, int W, int H, int tx, int ty,
+                                    float gw) {
+  constexpr int N = T - T0;
+  float v[N][C];
+  const int bx = clampi(tx + L.dx, 0, W - 1);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = 0.f;
-  ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
-  if constexpr (!FP16) {
-    bool live = false;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) live = live || (ok[b] && group_sum<T>(acc[b], base) < bound);
-    if (__ballot(live) == 0ull) return false;
+  for (int n = 0; n < N; ++n) {
+    const int by = clampi(ty + T0 + n - R, 0, H - 1);
+    Px<C, FP16>::load1(F2, by * W + bx, v[n]);
   }
-  ident_rows<R, C, FP16, NB, TE, T>(acc, L, F2, W, H, tx, ty, gw);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) cost[b] = group_sum<T>(acc[b], base);
-  return true;
+  for (int n = 0; n < N; ++n) acc += tap_sq<C>(L.f1[T0 + n], v[n], gw);
+  return acc;
 }
 
+// Rows [T0, T) of one identity-patch target in steps of kIdentStep rows, the
+// group sum checked against bound before each step: false (and the rows
+// computed added to rows) as soon as a partial sum is >= bound; otherwise a =
+// the full lane partial and rows += T.
+template <int R, int C, bool FP16, int T0>
+__device__ inline bool ident_finish(float& a, float acc, const LaneCol<R, C, true>& L, Feat F2, int W, int H,
+                                    int tx, int ty, float gw, int base, float bound, unsigned& rows) {
+  constexpr int T = 2 * R + 1, T1 = T0 + kIdentStep < T ? T0 + kIdentStep : T;
+  acc = ident_rows1<R, C, FP16, T0, T1>(acc, L, F2, W, H, tx, ty, gw);
+  if constexpr (T1 == T) {
+    a = acc;
+    rows += T;
+    return true;
+  } else {
+    if (!(group_sum<T>(acc, base) < bound)) {
+      rows += T1;
+      return false;
+    }
+    return ident_finish<R, C, FP16, T1>(a, acc, L, F2, W, H, tx, ty, gw, base, bound, rows);
+  }
+}
+
+// One identity-patch batch: NB targets, compared with the best in candidate
+// order (a candidate replaces it only if strictly better), with the decisions
+// of a one-at-a-time loop.  The first third of the rows of every target is
+// gathered together; then each target still in the running is finished on its
+// own, unless its partial sum is already >= the current best cost: taps are
+// non-negative and FP32 addition is monotone, so its full cost could not be
+// strictly lower, and its remaining rows are skipped.  The check is per lane
+// group: the lanes of a dropped target sit out its remaining gathers, which
+// is where the time goes (the cost of a gather scales with the lanes that
+// take part in it).  A finished target is summed in the same order as a lone
+// evaluation.  FP16 records (one load per tap) gather all rows of the batch
+// together and skip the checks: measured on MI355X, finishing each target on
+// its own makes the FP16 pipeline 3 % slower.
 template <int R, int C, bool FP16, int NB>
 __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                    const int* ty, const bool* ok, float gw, int base, int& btx, int& bty, float& bc,
@@ -524,19 +551,48 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
 #pragma unroll
   for (int b = 0; b < NB; ++b) any = any || ok[b];
   if (!any) return;
-  float c[NB];
-  const bool full = group_cost_ident_batch<R, C, FP16, NB>(L, F2, W, H, tx, ty, ok, bc, gw, base, c);
+  float acc[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    if (!ok[b]) continue;
-    ++evals;
-    rows += full ? T : TE;
-    if (!full) continue;
-    if (tx[b] == btx && ty[b] == bty) continue;
-    if (c[b] < bc) {
-      bc = c[b];
-      btx = tx[b];
-      bty = ty[b];
+  for (int b = 0; b < NB; ++b) acc[b] = 0.f;
+  if constexpr (FP16) {
+    ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
+    ident_rows<R, C, FP16, NB, TE, T>(acc, L, F2, W, H, tx, ty, gw);
+    float c[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) c[b] = group_sum<T>(acc[b], base);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (!ok[b]) continue;
+      ++evals;
+      rows += T;
+      if (tx[b] == btx && ty[b] == bty) continue;
+      if (c[b] < bc) {
+        bc = c[b];
+        btx = tx[b];
+        bty = ty[b];
+      }
+    }
+  } else {
+    ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
+    float pre[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pre[b] = group_sum<T>(acc[b], base);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (!ok[b]) continue;
+      ++evals;
+      if ((tx[b] == btx && ty[b] == bty) || !(pre[b] < bc)) {
+        rows += TE;
+        continue;
+      }
+      float a;
+      if (!ident_finish<R, C, FP16, TE>(a, acc[b], L, F2, W, H, tx[b], ty[b], gw, base, bc, rows)) continue;
+      const float c = group_sum<T>(a, base);
+      if (c < bc) {
+        bc = c;
+        btx = tx[b];
+        bty = ty[b];
+      }
     }
   }
 }
