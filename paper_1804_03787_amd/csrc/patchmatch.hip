@@ -80,6 +80,40 @@ struct Px {
       }
     }
   }
+  // The record of pixel idx as raw words (kWords of them), for tap_sq_raw.
+  static constexpr int kWords = kBytes / 4;
+  static __device__ inline void raw1(Feat F, int idx, uint32_t* u) {
+    const int o = idx * kBytes;
+    if constexpr (kWords == 5) {
+      const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+      u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+      u[4] = __builtin_amdgcn_raw_buffer_load_b32(F.r, o + 16, 0, 0);
+    } else if constexpr (kWords == 3) {
+      const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(F.r, o, 0, 0);
+      u[0] = a.x; u[1] = a.y; u[2] = a.z;
+    } else {
+      const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(F.r, o, 0, 0);
+      u[0] = a.x; u[1] = a.y;
+    }
+  }
+  // Records of pixels idx and idx + 1 as raw words (2 kWords), one access.
+  static __device__ inline void raw2(Feat F, int idx, uint32_t* u) {
+    const int o = idx * kBytes;
+    if constexpr (kWords == 5) {
+      const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+      const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(F.r, o + 16, 0, 0);
+      const u32x2 c = __builtin_amdgcn_raw_buffer_load_b64(F.r, o + 32, 0, 0);
+      u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w; u[4] = b.x;
+      u[5] = b.y; u[6] = b.z; u[7] = b.w; u[8] = c.x; u[9] = c.y;
+    } else if constexpr (kWords == 3) {
+      const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+      const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(F.r, o + 16, 0, 0);
+      u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w; u[4] = b.x; u[5] = b.y;
+    } else {
+      const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
+      u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+    }
+  }
   static __device__ inline void load2(Feat F, int idx, float* v, float* w) {
     const int o = idx * kBytes;
     if constexpr (!FP16) {
@@ -199,6 +233,70 @@ __device__ inline float tap_sq(const float* f1, const float* v, float gw) {
   return row;
 }
 
+// f - h for the FP16 value h in the low (HI = false) or high half of u: the
+// half is widened exactly and the difference rounded once, as a conversion
+// followed by an FP32 subtraction gives, but in one mixed-precision
+// multiply-add (h * -1 + f) instead of two instructions.
+template <bool HI>
+__device__ inline float sub_half(float f, uint32_t u) {
+  float e;
+  if constexpr (HI)
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(e) : "v"(u), "v"(f));
+  else
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(e) : "v"(u), "v"(f));
+  return e;
+}
+
+// h * w + acc and h * w + 0 for the FP16 value h in the low or high half of u,
+// rounded once, with h widened exactly: the values a conversion followed by
+// an FP32 multiply-add (or multiply) gives, up to the sign of an exact zero
+// product, which no tap cost can tell apart (it only ever reaches a square).
+template <bool HI>
+__device__ inline float fma_half(uint32_t u, float w, float acc) {
+  float r;
+  if constexpr (HI)
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(w), "v"(acc));
+  else
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(w), "v"(acc));
+  return r;
+}
+template <bool HI>
+__device__ inline float mul_half(uint32_t u, float w) {
+  float r;
+  if constexpr (HI)
+    asm("v_fma_mix_f32 %0, %1, %2, 0 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(w));
+  else
+    asm("v_fma_mix_f32 %0, %1, %2, 0 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(u), "v"(w));
+  return r;
+}
+
+// Channel k of the record whose raw words start at u (FP16: widened).
+template <int C, bool FP16>
+__device__ inline float chan(const uint32_t* u, int k) {
+  if constexpr (FP16) {
+    const uint32_t x = u[k >> 1];
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)((k & 1) ? (x >> 16) : (x & 0xffffu)));
+  } else {
+    return uf(u[k]);
+  }
+}
+
+// tap_sq of a record in its raw words (Px::raw1): the same value.
+template <int C, bool FP16>
+__device__ inline float tap_sq_raw(const float* f1, const uint32_t* u, float gw) {
+  float row = 0.f;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    float e;
+    if constexpr (FP16)
+      e = (k & 1) ? sub_half<true>(f1[k], u[k >> 1]) : sub_half<false>(f1[k], u[k >> 1]);
+    else
+      e = f1[k] - uf(u[k]);
+    row = (k < 3) ? fmaf(e, e, row) : fmaf(gw * e, e, row);
+  }
+  return row;
+}
+
 // Sum of the group's column partials in lane order, identical on every lane
 // of the group.  Eight adds with the wave shifted right by one lane leave at
 // lane l the sum ((v[l-G+1] + v[l-G+2]) + ...) + v[l]; at the group's last lane
@@ -272,7 +370,7 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat 
     return add_rows<R, C, FP16, IDENT, INTEGRAL, T0 + 3, T1>(acc, L, F2, W, H, tx, ty, gw);
   } else if constexpr (IDENT || INTEGRAL) {
     constexpr int N = T1 - T0;
-    float v[N][C];
+    uint32_t v[N][Px<C, FP16>::kWords];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const int t = T0 + n;
@@ -284,15 +382,16 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat 
         bx = clampi(tx + L.ox(t), 0, W - 1);
         by = clampi(ty + L.oy(t), 0, H - 1);
       }
-      Px<C, FP16>::load1(F2, by * W + bx, v[n]);
+      Px<C, FP16>::raw1(F2, by * W + bx, v[n]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int n = 0; n < N; ++n) acc += tap_sq<C>(L.f1[T0 + n], v[n], gw);
+    for (int n = 0; n < N; ++n) acc += tap_sq_raw<C, FP16>(L.f1[T0 + n], v[n], gw);
     return acc;
   } else {
-    constexpr int N = T1 - T0;
-    float a[N][C], b[N][C], c[N][C], d[N][C], fx[N], fy[N];
+    constexpr int N = T1 - T0, KW = Px<C, FP16>::kWords;
+    uint32_t top[N][2 * KW], bot[N][2 * KW];
+    float fx[N], fy[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const int t = T0 + n;
@@ -304,8 +403,8 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat 
       fy[n] = (unsigned)uy < (unsigned)(H - 1) ? L.fy[t] : 0.f;
       const int i0 = by * W + bx;
       const int i1 = i0 + (by < H - 1 ? W : 0);
-      Px<C, FP16>::load2(F2, i0, a[n], b[n]);
-      Px<C, FP16>::load2(F2, i1, c[n], d[n]);
+      Px<C, FP16>::raw2(F2, i0, top[n]);
+      Px<C, FP16>::raw2(F2, i1, bot[n]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -314,7 +413,22 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat 
       const float w00 = gx * gy, w01 = fx[n] * gy, w10 = gx * fy[n], w11 = fx[n] * fy[n];
       float v[C];
 #pragma unroll
-      for (int k = 0; k < C; ++k) v[k] = fmaf(w11, d[n][k], fmaf(w10, c[n][k], fmaf(w01, b[n][k], w00 * a[n][k])));
+      for (int k = 0; k < C; ++k) {
+        if constexpr (FP16) {
+          // corners a, b (top pair) and c, d (bottom pair), widened inside the FMAs
+          const int wi = k >> 1;
+          if (k & 1)
+            v[k] = fma_half<true>(bot[n][KW + wi], w11, fma_half<true>(bot[n][wi], w10,
+                   fma_half<true>(top[n][KW + wi], w01, mul_half<true>(top[n][wi], w00))));
+          else
+            v[k] = fma_half<false>(bot[n][KW + wi], w11, fma_half<false>(bot[n][wi], w10,
+                   fma_half<false>(top[n][KW + wi], w01, mul_half<false>(top[n][wi], w00))));
+        } else {
+          v[k] = fmaf(w11, chan<C, FP16>(bot[n] + KW, k),
+                      fmaf(w10, chan<C, FP16>(bot[n], k),
+                           fmaf(w01, chan<C, FP16>(top[n] + KW, k), w00 * chan<C, FP16>(top[n], k))));
+        }
+      }
       acc += tap_sq<C>(L.f1[T0 + n], v, gw);
     }
     return acc;
@@ -467,7 +581,7 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
 #pragma unroll
   for (int t0 = T0; t0 < T; t0 += kIdentRows) {
     constexpr int TC = kIdentRows;
-    float v[TC][NB][C];
+    uint32_t v[TC][NB][Px<C, FP16>::kWords];
 #pragma unroll
     for (int u = 0; u < TC; ++u)
 #pragma unroll
@@ -475,7 +589,7 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
         if (t0 + u < T) {
           const int bx = clampi(tx[b] + L.dx, 0, W - 1);
           const int by = clampi(ty[b] + t0 + u - R, 0, H - 1);
-          Px<C, FP16>::load1(F2, by * W + bx, v[u][b]);
+          Px<C, FP16>::raw1(F2, by * W + bx, v[u][b]);
         }
       }
     __builtin_amdgcn_sched_barrier(0);
@@ -483,7 +597,7 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
     for (int u = 0; u < TC; ++u)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
-        if (t0 + u < T) acc[b] += tap_sq<C>(L.f1[t0 + u], v[u][b], gw);
+        if (t0 + u < T) acc[b] += tap_sq_raw<C, FP16>(L.f1[t0 + u], v[u][b], gw);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -494,16 +608,16 @@ template <int R, int C, bool FP16, int T0, int T>
 __device__ inline float ident_rows1(float acc, const LaneCol<R, C, true>& L, Feat F2, int W, int H, int tx, int ty,
                                     float gw) {
   constexpr int N = T - T0;
-  float v[N][C];
+  uint32_t v[N][Px<C, FP16>::kWords];
   const int bx = clampi(tx + L.dx, 0, W - 1);
 #pragma unroll
   for (int n = 0; n < N; ++n) {
     const int by = clampi(ty + T0 + n - R, 0, H - 1);
-    Px<C, FP16>::load1(F2, by * W + bx, v[n]);
+    Px<C, FP16>::raw1(F2, by * W + bx, v[n]);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int n = 0; n < N; ++n) acc += tap_sq<C>(L.f1[T0 + n], v[n], gw);
+  for (int n = 0; n < N; ++n) acc += tap_sq_raw<C, FP16>(L.f1[T0 + n], v[n], gw);
   return acc;
 }
 
