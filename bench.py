@@ -14,8 +14,12 @@ hypotheses per window, FP32 patch costs, FP64 plane fits.
 
 Prints one JSON line: flow Mpix/s of the timed steps (each step one launch of
 the pipeline captured as a HIP graph, msgpm_solve_graph; --no-graph: eager
-launches), the dominant kernel's roofline (from an equal number of eager steps
-timed with HIP events around each launch) and the FP64 CPU oracle (its OpenMP
+launches); per PatchMatch kernel (identity patches of the initial pass and of
+the restricted passes, distorted patches) its own time (an equal number of
+eager steps with the restricted launches in sequence on one stream, HIP events
+around each launch) against the chip's FP32 ALU, HBM and LDS peaks and against
+the measured gather ceiling of its access pattern (libmsgpm_ceiling); the
+dominant kernel's entry as the roofline; and the FP64 CPU oracle (its OpenMP
 build, all of this host's cores) timed on the same 1024x436 pair.
 
 Other workloads: --fp16 (FP16 feature storage), --cues (occlusion cues 2 and
@@ -40,17 +44,69 @@ if ROOT not in sys.path:
 
 W, H = 1024, 436
 PARAMS = dict(C=5, r=4, blocks=(64, 32, 16), iters=8, hyps=256, tau=1.0, eps=0.1, tau_fb=1.0, seed=0)
-PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
+# MI355X peaks: vector FP32 with packed (dual-issue) FMA 157.3 TFLOP/s (256 CU x
+# 2.4 GHz x 256 flop/clk); without packing 78.6 (the kernels are built without
+# packed FP32 instructions); HBM3E 8 TB/s; LDS 160 KB per CU at 128 B/clk
+# (256 x 2.4 GHz x 128 B = 78.6 TB/s).
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+PEAK_LDS_GBS = 78643.2
 
-# HBM bytes per launch of each PatchMatch kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and 1.0: what the
-# counters read for a plain 256 MiB copy), averaged over the launches of one
-# pipeline run; None when not measured for the kernels as they are now.
+# Bytes beyond L2 per launch of each PatchMatch kernel on the 1024x436 workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, scaled by 2.0 and
+# 1.0: what the counters read for a plain 256 MiB copy), averaged over the
+# dispatches of one pipeline run (identity: the initial pass's and the
+# restricted ones'); keyed by storage.  None where not measured for the
+# kernels as they are now.
 TRAFFIC = {
     # profiles/k_pm_halfsweep_1024x436_traffic.md
-    "k_pm_halfsweep (identity patches)": 1.526e9,
-    "k_pm_halfsweep (distorted patches)": 3.411e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", False): 1.9669e9,
+    ("k_pm_halfsweep (identity patches, restricted)", False): 4.9824e8,
+    ("k_pm_halfsweep (distorted patches)", False): 3.3994e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", True): 9.8935e8,
+    ("k_pm_halfsweep (identity patches, restricted)", True): 3.2276e8,
+    ("k_pm_halfsweep (distorted patches)", True): 1.5298e8,
 }
+
+
+def gather_ceiling(W: int, H: int, r: int, record_words: int, bilinear: bool, patches: int = 15,
+                   reps: int = 5) -> float:
+    """Patches per second of libmsgpm_ceiling's gather kernel: the PatchMatch
+    kernels' gathers (lane groups per pixel of one colour, each gathering the
+    patches of a candidate stream of 4 propagations and one target per search
+    radius) with none of their arithmetic, on a W x H frame of records of
+    record_words words; the best of `reps` launches."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1804_03787_amd", "libmsgpm_ceiling.so"))
+    lib.msgpm_ceiling_blocks.argtypes = [ctypes.c_int] * 3
+    lib.msgpm_ceiling_gather.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p]
+    nb = lib.msgpm_ceiling_blocks(W, H, r)
+    if nb <= 0:
+        raise RuntimeError("gather ceiling: frame size or radius out of range")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    feat = torch.rand((W * H + 1) * record_words, device="cuda", generator=g)
+    sink = torch.empty(nb * 256, dtype=torch.int32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    best = None
+    for k in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        st = lib.msgpm_ceiling_gather(ctypes.c_void_p(feat.data_ptr()), W, H, record_words, r, int(bilinear),
+                                      patches, 1234 + k, ctypes.c_void_p(sink.data_ptr()), stream)
+        b.record()
+        if st != 0:
+            raise RuntimeError(f"gather ceiling launch failed ({st})")
+        b.synchronize()
+        if k:  # the first launch warms up
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+    groups = ((W + 1) // 2) * H
+    return groups * patches / (best * 1e-3)
 
 
 def flops_per_eval(kind: str, r: int, C: int) -> int:
@@ -378,6 +434,9 @@ def main() -> int:
                     help="time eager launches only (default: the pipeline as one captured HIP graph per step, "
                          "plus an eager pass with HIP events around every launch for the per-kernel figures)")
     ap.add_argument("--fp16", action="store_true", help="FP16 feature storage (FP32 accumulation)")
+    ap.add_argument("--two-streams", action="store_true",
+                    help="restricted half-sweeps' two launches side by side on two streams (library default) "
+                         "instead of in sequence on one")
     ap.add_argument("--seed", type=int, default=0, help="scene seed of the 1024x436 generator")
     ap.add_argument("--cues", action="store_true", help="occlusion cues 2 (uniqueness) and 3 (overlap) on")
     ap.add_argument("--fill", type=int, default=0, help="half-sweeps of filling by model propagation (0 = none)")
@@ -415,7 +474,7 @@ def main() -> int:
     f1 = torch.from_numpy(pair.frame1).cuda()
     f2 = torch.from_numpy(pair.frame2).cuda()
     params = dict(PARAMS, fp16=args.fp16, cue_overlap=args.cues, cue_unique=args.cues, fill_sweeps=args.fill,
-                  histeq=args.histeq, merge_strict=args.strict)
+                  histeq=args.histeq, merge_strict=args.strict, one_stream=not args.two_streams)
     g = msgpm.Pair(W, H, **params)
     flows = [torch.empty((H, W, 2), dtype=torch.float32, device="cuda") for _ in range(2)]
     occs = [torch.empty((H, W), dtype=torch.uint8, device="cuda") for _ in range(2)]
@@ -481,27 +540,81 @@ def main() -> int:
     kernel_ms = {k: v[0] / args.steps for k, v in timing.items()}
     launches = {k: v[1] / args.steps for k, v in timing.items()}
     r, C = params["r"], params["C"]
-    # the two PatchMatch kernels: identity patches (initial pass and restricted
-    # pixels without a region plane) and distorted patches (restricted pixels with one)
-    kernels = {
-        "k_pm_halfsweep (identity patches)": (
-            kernel_ms["pm_init"] + kernel_ms["pm_restricted_ident"],
-            launches["pm_init"] + launches["pm_restricted_ident"],
-            (full["pm_init"] + full["pm_restricted_ident"]) * flops_per_eval("identity", r, C)),
-        "k_pm_halfsweep (distorted patches)": (
-            kernel_ms["pm_restricted"], launches["pm_restricted"],
-            full["pm_restricted"] * flops_per_eval("warped", r, C)),
-    }
-    dominant = max(kernels, key=lambda k: kernels[k][0])
-    dom_ms, dom_launches, dom_flops = kernels[dominant]
+
+    # each PatchMatch kernel on its own: by default the restricted half-sweeps'
+    # two launches run in sequence on one stream (MSGPM_FLAG_ONE_STREAM), so the
+    # timed eager steps give each kernel's own time; with --two-streams they
+    # run side by side there, and an equal number of one-stream steps is timed
+    alone_ms, alone_n = kernel_ms, launches
+    if args.two_streams:
+        g1 = msgpm.Pair(W, H, **dict(params, one_stream=True))
+        g1.solve(f1, f2)
+        torch.cuda.synchronize()
+        msgpm.timing_enable(True)
+        msgpm.timing_read()
+        for _ in range(args.steps):
+            g1.solve(f1, f2)
+        torch.cuda.synchronize()
+        alone = msgpm.timing_read()
+        msgpm.timing_enable(False)
+        del g1
+        alone_ms = {k: v[0] / args.steps for k, v in alone.items()}
+        alone_n = {k: v[1] / args.steps for k, v in alone.items()}
+        print("bench: timed the steps with one stream", file=sys.stderr, flush=True)
+
+    words = (3 if C == 5 else 2) if args.fp16 else C
+    ceil_ident = gather_ceiling(W, H, r, words, False)
+    ceil_bilin = gather_ceiling(W, H, r, words, True)
+    print(f"bench: gather ceiling {ceil_ident / 1e9:.2f} G identity patches/s, {ceil_bilin / 1e9:.2f} G bilinear",
+          file=sys.stderr, flush=True)
+
+    # per kernel: tap rows computed (a candidate dropped by early rejection
+    # counts the rows it gathered) as full-patch equivalents; flops of those
+    # rows; bytes beyond L2 from the counters; LDS none (no kernel stages tiles)
+    kernels = {}
+    for name, kind, ck, ident, ceil in (
+            ("k_pm_halfsweep (identity patches, initial pass)", "pm_init", "pm_init", True, ceil_ident),
+            ("k_pm_halfsweep (identity patches, restricted)", "pm_restricted_ident", "pm_restricted_ident", True,
+             ceil_ident),
+            ("k_pm_halfsweep (distorted patches)", "pm_restricted", "pm_restricted", False, ceil_bilin)):
+        ms, n = alone_ms.get(kind, 0.0), alone_n.get(kind, 0.0)
+        if ms <= 0 or n <= 0:
+            continue
+        patches = full[ck]
+        flops = patches * flops_per_eval("identity" if ident else "warped", r, C)
+        tflops = flops / (ms * 1e-3) / 1e12
+        traffic = TRAFFIC.get((name, bool(args.fp16)))
+        launch_s = ms * 1e-3 / n
+        hbm_gbs = traffic / launch_s / 1e9 if traffic else None
+        kernels[name] = {
+            "ms_per_step": round(ms, 3), "launches_per_step": n, "avg_launch_us": round(launch_s * 1e6, 2),
+            "evals_per_s": round(ev[ck] / (ms * 1e-3), 1),
+            "full_patch_equiv_per_s": round(patches / (ms * 1e-3), 1),
+            "gather_ceiling_patches_per_s": round(ceil, 1), "gather_frac": round(patches / (ms * 1e-3) / ceil, 4),
+            "alu_tflops": round(tflops, 3), "alu_frac": round(tflops / PEAK_FP32_TFLOPS, 4),
+            "alu_frac_nonpacked": round(tflops / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "hbm_bytes_per_launch": traffic, "hbm_gbs": round(hbm_gbs, 1) if hbm_gbs else None,
+            "hbm_frac": round(hbm_gbs / PEAK_HBM_GBS, 4) if hbm_gbs else None,
+            "lds_bytes_per_launch": 0, "lds_frac": 0.0,
+        }
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
     roofline = None
-    if dom_ms > 0:
-        achieved = dom_flops / (dom_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": TRAFFIC.get(dominant),
-                    "traffic_unit": "bytes per launch",
-                    "kernel": dominant, "ms_per_step": round(dom_ms, 3),
-                    "avg_launch_us": round(dom_ms * 1e3 / max(dom_launches, 1), 2)}
+    if dominant:
+        k = kernels[dominant]
+        roofline = {"bound": "alu", "achieved": k["alu_tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": k["alu_frac"], "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
+                    "frac_nonpacked": k["alu_frac_nonpacked"],
+                    "traffic": k["hbm_bytes_per_launch"], "traffic_unit": "bytes per launch (beyond L2)",
+                    "kernel": dominant, "ms_per_step": k["ms_per_step"], "avg_launch_us": k["avg_launch_us"],
+                    "gather_frac": k["gather_frac"], "hbm_frac": k["hbm_frac"], "lds_frac": 0.0}
+    warped = kernels.get("k_pm_halfsweep (distorted patches)")
+    target = None
+    if warped:
+        best = max(warped["hbm_frac"] or 0.0, warped["lds_frac"])
+        target = {"kernel": "k_pm_halfsweep (distorted patches)", "hbm_lds_frac": best, "target": 0.5,
+                  "met": best >= 0.5, "gather_frac": warped["gather_frac"],
+                  "note": "the warped-SSD kernel moves its bytes through L1/L2 gathers; beyond-L2 traffic is "
+                          "the HBM figure, and it stages nothing in LDS"}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -526,7 +639,8 @@ def main() -> int:
                                "8 PM iterations, 256 RANSAC hypotheses",
                    "width": W, "height": H, "seed": args.seed, "fp16_storage": bool(args.fp16),
                    "occlusion_cues_2_3": bool(args.cues), "fill_sweeps": args.fill, "histeq": bool(args.histeq),
-                   "merge_strict": bool(args.strict), "independent_quads": bool(args.independent)},
+                   "merge_strict": bool(args.strict), "independent_quads": bool(args.independent),
+                   "restricted_launches": "two streams" if args.two_streams else "one stream"},
         "patch_evals_per_s": round((ev["pm_init"] + ev["pm_restricted"] + ev["pm_restricted_ident"])
                                    / (ms_per_step * 1e-3), 1),
         # the initial pass alone: its evaluations over its kernel time, beside the
@@ -543,6 +657,8 @@ def main() -> int:
         "launch": "hip graph per step" if use_graph else "eager",
         "eager_ms_per_step": round(eager_ms, 3),
         "roofline": roofline,
+        "roofline_kernels": kernels,
+        "warped_ssd_hbm_lds_target": target,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

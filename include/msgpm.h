@@ -84,6 +84,17 @@ typedef enum msgpm_status {
    incumbent when its loss is strictly smaller, the level breaking exact ties
    in favour of the coarser one (key (L, level, stage, window)). */
 #define MSGPM_FLAG_MERGE_STRICT 16u
+/* Execution option, not part of the method: the two launches of each
+   restricted half-sweep (pixels with a region plane, pixels without) are
+   issued one after the other on the caller's stream instead of side by side
+   on the caller's stream and a second stream of the library's.  Results are
+   the same either way (the two launches update disjoint pixels and read only
+   the other colour); with the flag the library creates no second stream, and
+   the per-kind kernel times of msgpm_timing_read are each kernel's own,
+   without the other's interference.  msgpm_solve_static always runs this
+   way.  Ignored by the batched and served forms, which take every pair's
+   restricted half-sweep in shared launches of their own. */
+#define MSGPM_FLAG_ONE_STREAM 32u
 
 /* Method parameters.  Defaults in brackets are those of the 1024x436 workload. */
 typedef struct msgpm_params {

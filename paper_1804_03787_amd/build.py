@@ -1,4 +1,5 @@
-"""Builds libmsgpm.so (HIP, gfx950) in the package directory with hipcc.
+"""Builds libmsgpm.so (HIP, gfx950) in the package directory with hipcc, and
+libmsgpm_ceiling.so, the benchmark's gather-ceiling measurement kernel.
 
 Every translation unit is compiled with contraction off (explicit fmaf where a
 fused multiply-add is wanted) and without packed-FP32 instruction selection.
@@ -14,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsgpm.so")
 SOURCES = ["host.hip", "init.hip", "patchmatch.hip", "planes.hip"]
+CEILING_OUT = os.path.join(HERE, "libmsgpm_ceiling.so")
+CEILING_SOURCE = "ceiling.hip"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -31,19 +34,24 @@ def _compile(src: str, build_dir: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    build_dir = os.path.join(HERE, "_build")
-    os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir, verbose), SOURCES))
-    tmp = OUT + ".tmp"
+def _link(objs, out: str, libs, verbose: bool) -> None:
+    tmp = out + ".tmp"
     rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L", os.path.join(rocm, "lib"),
-           "-lrocprofiler-sdk-roctx", "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L", os.path.join(rocm, "lib"), *libs,
+           "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    build_dir = os.path.join(HERE, "_build")
+    os.makedirs(build_dir, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(lambda s: _compile(s, build_dir, verbose), SOURCES + [CEILING_SOURCE]))
+    _link(objs[:-1], OUT, ["-lrocprofiler-sdk-roctx"], verbose)
+    _link(objs[-1:], CEILING_OUT, [], verbose)
     return OUT
 
 

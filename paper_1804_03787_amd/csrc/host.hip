@@ -151,7 +151,7 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
       !(p->grad_weight >= 0))
     return fail(MSGPM_E_INVALID, "thresholds must be positive and finite");
   if (p->flags & ~(MSGPM_FLAG_FP16 | MSGPM_FLAG_CUE_OVERLAP | MSGPM_FLAG_CUE_UNIQUE | MSGPM_FLAG_HISTEQ |
-                   MSGPM_FLAG_MERGE_STRICT))
+                   MSGPM_FLAG_MERGE_STRICT | MSGPM_FLAG_ONE_STREAM))
     return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->fill_sweeps < 0 || p->fill_sweeps > 65536) return fail(MSGPM_E_INVALID, "fill_sweeps outside 0..65536");
   {
@@ -281,6 +281,7 @@ msgpm_status open_ctx(const msgpm_params* p, void* ws, void* stream, Ctx* c) {
   if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MSGPM_E_INVALID, "workspace not 256-byte aligned");
   c->w = make_ws(c->P, c->L, ws);
   c->s = static_cast<hipStream_t>(stream);
+  c->one_stream = (p->flags & MSGPM_FLAG_ONE_STREAM) != 0;
   return MSGPM_OK;
 }
 
@@ -344,9 +345,13 @@ msgpm_status run_halfsweep(const Ctx& c, int colour, int it, int slot, int restr
   if (c.one_stream) {
     // the two launches update disjoint pixels and read only the other colour:
     // in sequence they give the same result as side by side
-    msgpm_status st = check(launch_pm_restricted(c.P, c.w, colour, it, slot, 0, fresh, c.s), "pm_restricted");
+    msgpm_status st = check(timed(MSGPM_T_PM_RESTRICTED, c.s, [&] {
+      return launch_pm_restricted(c.P, c.w, colour, it, slot, 0, fresh, c.s);
+    }), "pm_restricted");
     if (st != MSGPM_OK) return st;
-    return check(launch_pm_restricted(c.P, c.w, colour, it, slot, 1, fresh, c.s), "pm_restricted");
+    return check(timed(MSGPM_T_PM_RESTRICTED_IDENT, c.s, [&] {
+      return launch_pm_restricted(c.P, c.w, colour, it, slot, 1, fresh, c.s);
+    }), "pm_restricted");
   }
   // distorted patches on the caller's stream, identity patches on the second one
   return side_by_side(
@@ -611,7 +616,7 @@ msgpm_status msgpm_solve_graph(const msgpm_params* p, const float* d_rgb1, const
   std::string key(reinterpret_cast<const char*>(p), sizeof *p);
   key.append(reinterpret_cast<const char*>(ptrs), sizeof ptrs);
   Aux* aux = nullptr;  // created outside the capture; joins it through the fork event
-  if ((st = check(aux_stream(&aux), "second stream")) != MSGPM_OK) return st;
+  if (!c.one_stream && (st = check(aux_stream(&aux), "second stream")) != MSGPM_OK) return st;
   return cached_graph_launch(key, c.s, [&](hipStream_t cs) {
     Ctx cc = c;
     cc.s = cs;

@@ -21,6 +21,7 @@ FLAG_CUE_OVERLAP = 2  # occlusion cue 3: plane kept only if its consistent pixel
 FLAG_CUE_UNIQUE = 4   # occlusion cue 2: one assigned pixel per target
 FLAG_HISTEQ = 8       # equalise the frames' HSV value channel before the features
 FLAG_MERGE_STRICT = 16  # strict level priority: a later level assigns only unassigned pixels
+FLAG_ONE_STREAM = 32  # restricted half-sweeps' two launches in sequence on the caller's stream
 PM_FRESH = 2          # pm_halfsweep: compute each swept pixel's current cost first (folds the cost refresh in)
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_DEVICE", 4: "E_UNSUPPORTED", 5: "E_BUSY", 6: "E_CANCELLED",
@@ -167,7 +168,8 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
                 hyps: int = 256, R0: int = 0, tau: float = 1.0, eps: float = 0.1, tau_fb: float = 1.0,
                 mu: float = 0.25, m_min_abs: int = 8, eta=(1, 2), seed: int = 0, fp16: bool = False,
                 grad_weight: float = 1.0, cue_overlap: bool = False, cue_unique: bool = False,
-                fill_sweeps: int = 0, histeq: bool = False, merge_strict: bool = False) -> Params:
+                fill_sweeps: int = 0, histeq: bool = False, merge_strict: bool = False,
+                one_stream: bool = False) -> Params:
     p = Params()
     p.width, p.height, p.channels, p.patch_radius = width, height, C, r
     blocks = list(blocks)
@@ -178,7 +180,7 @@ def make_params(width: int, height: int, *, C: int = 5, r: int = 4, blocks=(64, 
     p.eta_num, p.eta_den = eta
     p.flags = ((FLAG_FP16 if fp16 else 0) | (FLAG_CUE_OVERLAP if cue_overlap else 0) |
                (FLAG_CUE_UNIQUE if cue_unique else 0) | (FLAG_HISTEQ if histeq else 0) |
-               (FLAG_MERGE_STRICT if merge_strict else 0))
+               (FLAG_MERGE_STRICT if merge_strict else 0) | (FLAG_ONE_STREAM if one_stream else 0))
     p.grad_weight, p.inlier_px, p.eps_color, p.fb_px, p.min_support_frac = grad_weight, tau, eps, tau_fb, mu
     p.seed = seed
     p.fill_sweeps = fill_sweeps

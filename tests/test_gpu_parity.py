@@ -357,6 +357,34 @@ def test_solve_is_deterministic():
     assert np.array_equal(outs[0][2].view(np.uint8), outs[1][2].view(np.uint8))
 
 
+def test_one_stream_flag_gives_the_same_result():
+    """MSGPM_FLAG_ONE_STREAM (both restricted launches in sequence on the
+    caller's stream) against the default two-stream issue: flow, masks, plane
+    table and NNF bit-identical, eager and as a captured graph, and the
+    restricted kinds are timed on their own."""
+    msgpm = _need_gpu()
+    pair = synth.planar_pair(160, 120, seed=3, scale=0.15)
+    outs = []
+    for one, graph in ((False, False), (True, False), (True, True)):
+        g = msgpm.Pair(160, 120, **_gpu_params(TINY_PARAMS), one_stream=one)
+        msgpm.timing_enable(not graph)
+        msgpm.timing_read()
+        fg, og = g.solve(pair.frame1, pair.frame2, graph=graph)
+        torch.cuda.synchronize()
+        tm = msgpm.timing_read()
+        msgpm.timing_enable(False)
+        if not graph:
+            assert tm["pm_restricted"][1] > 0 and tm["pm_restricted_ident"][1] > 0
+        outs.append(([f.cpu().numpy() for f in fg], [o.cpu().numpy() for o in og], g.planes(),
+                     [g.nnf(d).cpu().numpy() for d in range(2)]))
+    for other in outs[1:]:
+        for d in range(2):
+            assert np.array_equal(outs[0][0][d].view(np.uint32), other[0][d].view(np.uint32))
+            assert np.array_equal(outs[0][1][d], other[1][d])
+            assert np.array_equal(outs[0][3][d], other[3][d])
+        assert np.array_equal(outs[0][2].view(np.uint8), other[2].view(np.uint8))
+
+
 def test_invalid_arguments_raise():
     msgpm = _need_gpu()
     with pytest.raises(msgpm.MsgpmError):

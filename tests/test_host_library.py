@@ -22,6 +22,25 @@ def _declared():
     return sorted(set(re.findall(r"^\s*(?:msgpm_status|const char\s*\*)\s*(msgpm_\w+)\s*\(", text, flags=re.M)))
 
 
+def test_binding_constants_match_the_header():
+    """Flag bits and status codes of the Python binding are the header's."""
+    text = open(os.path.join(ROOT, "include", "msgpm.h")).read()
+    flags = dict(re.findall(r"#define MSGPM_FLAG_(\w+) (\d+)u", text))
+    assert flags, "no flags found"
+    for name, v in flags.items():
+        assert getattr(msgpm, "FLAG_" + name) == int(v), name
+    codes = dict(re.findall(r"MSGPM_(OK|E_\w+) = (\d+)", text))
+    assert len(codes) == 8
+    for name, v in codes.items():
+        assert msgpm.STATUS[int(v)] == name, name
+
+
+def test_one_stream_flag_is_accepted():
+    p = msgpm.make_params(1024, 436, one_stream=True)
+    assert p.flags & msgpm.FLAG_ONE_STREAM
+    assert msgpm.layout(p).total_bytes == msgpm.layout(msgpm.make_params(1024, 436)).total_bytes
+
+
 def test_library_exports_every_declared_function():
     names = _declared()
     assert len(names) >= 28, names
@@ -59,7 +78,9 @@ def test_layout_query_rejects_unknown_flags():
     assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) != 0
     p.flags = msgpm.FLAG_MERGE_STRICT
     assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) == 0
-    p.flags = 1 << 5
+    p.flags = msgpm.FLAG_ONE_STREAM
+    assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) == 0
+    p.flags = 1 << 6
     assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) != 0
     assert b"flags" in msgpm.lib().msgpm_last_error()
 
@@ -118,3 +139,20 @@ def test_oracle_matches_its_regression_anchor():
     for case in want:
         assert got[case]["frames_sha256"] == want[case]["frames_sha256"]
         assert got[case] == want[case], case
+
+
+def test_gather_ceiling_library_host_checks():
+    """libmsgpm_ceiling (the benchmark's gather-ceiling kernel): grid size and
+    argument checks run on the host; bad arguments launch nothing."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1804_03787_amd", "libmsgpm_ceiling.so"))
+    lib.msgpm_ceiling_blocks.argtypes = [ctypes.c_int] * 3
+    # one 9-lane group per pixel of one colour, 7 groups per wave, 4 waves per workgroup
+    assert lib.msgpm_ceiling_blocks(1024, 436, 4) == -(-(512 * 436) // 28)
+    assert lib.msgpm_ceiling_blocks(77, 53, 2) == -(-(39 * 53) // 48)
+    assert lib.msgpm_ceiling_blocks(1, 436, 4) == -1 and lib.msgpm_ceiling_blocks(64, 64, 5) == -1
+    lib.msgpm_ceiling_gather.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(0x10000000)
+    assert lib.msgpm_ceiling_gather(fake, 64, 48, 4, 2, 0, 15, 1, fake, None) == -1  # 4-word records
+    assert lib.msgpm_ceiling_gather(fake, 64, 48, 5, 2, 0, 0, 1, fake, None) == -1   # no patches
+    assert lib.msgpm_ceiling_gather(None, 64, 48, 5, 2, 0, 15, 1, fake, None) == -1
