@@ -307,3 +307,69 @@ def test_full_size_free_running_against_oracle_solve(case):
         print(case, "dir", d, rep, flush=True)
         assert rep["epe_delta"] <= 0.01, rep
         assert rep["nnf_unexplained_two_best"] == 0 and rep["occ_unexplained_two_best"] == 0, rep
+
+
+def _others():
+    """Two pairs of other sizes and scenes that share the batch or the server
+    with the full-size pair (same instantiation and schedule: windows 64/32/16)."""
+    return [(synth.planar_pair(640, 360, seed=21, scale=0.625), 21), (synth.planar_pair(320, 240, seed=22, scale=0.3125), 22)]
+
+
+def _check_against_golden(ref, g, flows, occs, label):
+    for d in range(2):
+        rep = parity.free_run_compare(ref[f"nnf{d}"], ref[f"occ{d}"], ref[f"flow{d}"], ref[f"pflag{d}"],
+                                      g.nnf(d).cpu().numpy(), occs[d].cpu().numpy(), flows[d].cpu().numpy())
+        print(label, "dir", d, rep, flush=True)
+        assert rep["epe_delta"] <= 0.01, rep
+        assert rep["nnf_unexplained_two_best"] == 0 and rep["occ_unexplained_two_best"] == 0, rep
+
+
+def test_full_size_batched_fp16_against_oracle_solve():
+    """The batched FP16-storage form at full size against the oracle: the scene
+    seed 1 1024x436 pair in one batch with a 640x360 and a 320x240 pair of other
+    scenes, the whole batch launched as one graph (msgpm_solve_batch_graph, as
+    bench.py --batched launches it), the full-size pair's NNF and masks bit-exact
+    against the stored whole oracle solve outside two-best near-ties, EPE delta
+    <= 0.01 px."""
+    msgpm = _need_gpu()
+    mod, ref = _golden("fp16_seed1")
+    pair = _pair(1)
+    assert [mod.digest(pair.frame1), mod.digest(pair.frame2)] == [str(s) for s in ref["frames_sha256"]]
+    scenes = [(pair, 0)] + _others()
+    gs = [msgpm.Pair(pr.shape[1], pr.shape[0], **_gpu_params(dict(FULL, fp16=True, seed=s))) for pr, s in scenes]
+    batch = msgpm.Batch(gs)
+    res = batch.solve([pr.frame1 for pr, _ in scenes], [pr.frame2 for pr, _ in scenes], graph=True)
+    torch.cuda.synchronize()
+    flows, occs = res[0]
+    _check_against_golden(ref, gs[0], flows, occs, "batched fp16_seed1")
+
+
+def test_full_size_served_fp16_against_oracle_solve():
+    """The served FP16-storage form at full size against the oracle: continuous
+    batching with the 1024x436 pair (scene seed 1) submitted while a 640x360
+    pair is in flight and before a 320x240 one, its result checked against the
+    stored whole oracle solve as in the batched test."""
+    msgpm = _need_gpu()
+    mod, ref = _golden("fp16_seed1")
+    pair = _pair(1)
+    others = _others()
+    srv = msgpm.Server(hbm_budget=1 << 34, max_active=8)
+    order = [(others[0][0], others[0][1]), (pair, 0), (others[1][0], others[1][1])]
+    tickets, done = {}, {}
+    for k, (pr, s) in enumerate(order):
+        g = msgpm.Pair(pr.shape[1], pr.shape[0], **_gpu_params(dict(FULL, fp16=True, seed=s)))
+        tickets[srv.submit(g, pr.frame1, pr.frame2)] = k
+        srv.step()
+    rounds = 0
+    while tickets:
+        srv.step()
+        for t, k in list(tickets.items()):
+            if srv.poll(t):
+                done[k] = srv.result(t)
+                del tickets[t]
+        rounds += 1
+        assert rounds < 1000000
+    srv.close()
+    g, flows, occs = done[1]
+    torch.cuda.synchronize()
+    _check_against_golden(ref, g, flows, occs, "served fp16_seed1")
