@@ -306,7 +306,7 @@ def run_serving(args) -> int:
     def serve(reqs, max_active=64, budget=200 << 30):
         """Returns (latencies in s, makespan in s, Mpix)."""
         srv = msgpm.Server(budget, max_active)
-        lat, out = [], {}
+        lat, out, cls = [], {}, []
         mpix = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] for _, c, _ in reqs) / 1e6
         torch.cuda.synchronize()
         start = time.perf_counter()
@@ -321,19 +321,21 @@ def run_serving(args) -> int:
             while k < len(reqs) and reqs[k][0] <= now:
                 t, c, j = reqs[k]
                 a, b = frames[(c, j)]
-                out[srv.submit(make_pair(c, True), a, b)] = t
+                out[srv.submit(make_pair(c, True), a, b)] = (t, c)
                 k += 1
             if out:
                 srv.step()
                 now = time.perf_counter() - start
                 for tk in [tk for tk in out if srv.poll(tk)]:
-                    lat.append(now - out.pop(tk))
+                    t0, c0 = out.pop(tk)
+                    lat.append(now - t0)
+                    cls.append(c0)
                     srv.result(tk)
             elif k < len(reqs):
                 time.sleep(max(0.0, reqs[k][0] - (time.perf_counter() - start)))
         span = time.perf_counter() - start
         srv.close()
-        return np.array(lat), span, mpix
+        return np.array(lat), span, mpix, np.array(cls)
 
     def one_at_a_time(reqs):
         pairs = {c: make_pair(c, False) for c in range(len(SERVE_SIZES))}
@@ -352,12 +354,21 @@ def run_serving(args) -> int:
             pairs[c].solve(a, b)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - start - t)
-        return np.array(lat), time.perf_counter() - start
+        return np.array(lat), time.perf_counter() - start, np.array([c for _, c, _ in reqs])
+
+    def per_class(lat, cls):
+        out = {}
+        for c, ((W, H), _, _) in enumerate(SERVE_SIZES):
+            sel = lat[cls == c]
+            if len(sel):
+                out[f"{W}x{H}"] = {"pairs": int(len(sel)), "p50_ms": round(float(np.median(sel)) * 1e3, 1),
+                                   "p99_ms": round(float(np.quantile(sel, 0.99)) * 1e3, 1)}
+        return out
 
     # capacity: every request of a trace submitted at time 0
     cap_reqs = [(0.0, c, j) for _, c, j in trace(args.rate, args.duration / 2, 4)]
     serve(cap_reqs[:8])  # warm-up
-    _, span, mpix = serve(cap_reqs)
+    _, span, mpix, _ = serve(cap_reqs)
     capacity = mpix / span
     print(f"bench: capacity {capacity:.2f} Mpix/s ({len(cap_reqs)} pairs in {span:.2f} s)", file=sys.stderr,
           flush=True)
@@ -386,19 +397,20 @@ def run_serving(args) -> int:
     runs = {}
     for label, rate in (("offered", args.rate), ("stable", 0.6 * capacity / mean_mpix)):
         reqs = trace(rate, args.duration, 4)
-        lat, span, mpix = serve(reqs)
+        lat, span, mpix, cls = serve(reqs)
         offered = rate * mean_mpix
         runs[label] = {"rate_pairs_s": round(rate, 2), "offered_mpix_s": round(offered, 2), "pairs": len(reqs),
                        "throughput_mpix_s": round(mpix / span, 3), "p50_ms": round(float(np.median(lat)) * 1e3, 1),
                        "p99_ms": round(float(np.quantile(lat, 0.99)) * 1e3, 1),
-                       "queue_stable": bool(offered < capacity)}
+                       "queue_stable": bool(offered < capacity), "by_size": per_class(lat, cls)}
         print(f"bench: {label} {runs[label]}", file=sys.stderr, flush=True)
     reqs = trace(runs["stable"]["rate_pairs_s"], args.duration, 4)
-    lat1, span1 = one_at_a_time(reqs)
+    lat1, span1, cls1 = one_at_a_time(reqs)
     mpix1 = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] for _, c, _ in reqs) / 1e6
     runs["stable_one_at_a_time_fp32"] = {"throughput_mpix_s": round(mpix1 / span1, 3),
                                          "p50_ms": round(float(np.median(lat1)) * 1e3, 1),
-                                         "p99_ms": round(float(np.quantile(lat1, 0.99)) * 1e3, 1)}
+                                         "p99_ms": round(float(np.quantile(lat1, 0.99)) * 1e3, 1),
+                                         "by_size": per_class(lat1, cls1)}
     line = {
         "metric": "serving: flow Mpix/s and p50/p99 pair latency",
         "value": runs["stable"]["throughput_mpix_s"],
