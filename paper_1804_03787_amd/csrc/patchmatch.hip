@@ -146,7 +146,10 @@ struct Px {
 
 // Per-lane state of one pixel: the lane's patch column of source features and,
 // for distorted patches, the tap geometry (integer offset + fraction of
-// Delta(d)) of that column, all in registers for every candidate.
+// Delta(d)) of that column, all in registers for every candidate.  FP16
+// records keep the column packed (the record's words in the first slots of
+// each f1[t]; 27 registers instead of 45 for C = 5), which takes the
+// distorted-patch kernel to 4 waves per SIMD without spills.
 template <int R, int C, bool IDENT>
 struct LaneCol {
   static constexpr int T = 2 * R + 1;
@@ -218,7 +221,16 @@ __device__ inline void load_column(LaneCol<R, C, IDENT>& L, Feat F1, int W, int 
 #pragma unroll
   for (int t = 0; t < 2 * R + 1; ++t) {
     const int cy = clampi(y + t - R, 0, H - 1);
-    Px<C, FP16>::load1(F1, cy * W + cx, L.f1[t]);
+    if constexpr (FP16) {
+      // FP16 records stay packed: the column's words in the first slots of
+      // f1[t] (bit copies), widened inside the tap arithmetic
+      uint32_t u[Px<C, FP16>::kWords];
+      Px<C, FP16>::raw1(F1, cy * W + cx, u);
+#pragma unroll
+      for (int k = 0; k < Px<C, FP16>::kWords; ++k) L.f1[t][k] = __builtin_bit_cast(float, u[k]);
+    } else {
+      Px<C, FP16>::load1(F1, cy * W + cx, L.f1[t]);
+    }
   }
 }
 
@@ -244,6 +256,34 @@ __device__ inline float sub_half(float f, uint32_t u) {
     asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(e) : "v"(u), "v"(f));
   else
     asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(e) : "v"(u), "v"(f));
+  return e;
+}
+
+// a - b for FP16 values a (half HA of ua) and b (half HB of ub), both widened
+// exactly and the difference rounded once (b * -1 + a).
+template <bool HA, bool HB>
+__device__ inline float sub_halves(uint32_t ua, uint32_t ub) {
+  float e;
+  if constexpr (HA && HB)
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(e) : "v"(ub), "v"(ua));
+  else if constexpr (HA)
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(e) : "v"(ub), "v"(ua));
+  else if constexpr (HB)
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(e) : "v"(ub), "v"(ua));
+  else
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,1]" : "=v"(e) : "v"(ub), "v"(ua));
+  return e;
+}
+
+// a - v for the FP16 value a (half HA of ua) and an FP32 v: a widened exactly,
+// the difference rounded once (v * -1 + a).
+template <bool HA>
+__device__ inline float sub_half_f32(uint32_t ua, float v) {
+  float e;
+  if constexpr (HA)
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(e) : "v"(v), "v"(ua));
+  else
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[0,0,1]" : "=v"(e) : "v"(v), "v"(ua));
   return e;
 }
 
@@ -288,10 +328,25 @@ __device__ inline float tap_sq_raw(const float* f1, const uint32_t* u, float gw)
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     float e;
-    if constexpr (FP16)
-      e = (k & 1) ? sub_half<true>(f1[k], u[k >> 1]) : sub_half<false>(f1[k], u[k >> 1]);
-    else
+    if constexpr (FP16) {
+      const uint32_t a = __builtin_bit_cast(uint32_t, f1[k >> 1]);
+      e = (k & 1) ? sub_halves<true, true>(a, u[k >> 1]) : sub_halves<false, false>(a, u[k >> 1]);
+    } else
       e = f1[k] - uf(u[k]);
+    row = (k < 3) ? fmaf(e, e, row) : fmaf(gw * e, e, row);
+  }
+  return row;
+}
+
+// tap_sq with the source record packed (FP16 words, as load_column keeps them)
+// and the target values in FP32: the same value as with the source widened first.
+template <int C>
+__device__ inline float tap_sq_packed(const float* f1, const float* v, float gw) {
+  float row = 0.f;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    const uint32_t a = __builtin_bit_cast(uint32_t, f1[k >> 1]);
+    const float e = (k & 1) ? sub_half_f32<true>(a, v[k]) : sub_half_f32<false>(a, v[k]);
     row = (k < 3) ? fmaf(e, e, row) : fmaf(gw * e, e, row);
   }
   return row;
@@ -429,7 +484,10 @@ __device__ inline float add_rows(float acc, const LaneCol<R, C, IDENT>& L, Feat 
                            fmaf(w01, chan<C, FP16>(top[n] + KW, k), w00 * chan<C, FP16>(top[n], k))));
         }
       }
-      acc += tap_sq<C>(L.f1[T0 + n], v, gw);
+      if constexpr (FP16)
+        acc += tap_sq_packed<C>(L.f1[T0 + n], v, gw);
+      else
+        acc += tap_sq<C>(L.f1[T0 + n], v, gw);
     }
     return acc;
   }
