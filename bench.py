@@ -64,9 +64,9 @@ TRAFFIC = {
     ("k_pm_halfsweep (identity patches, initial pass)", False): 1.9669e9,
     ("k_pm_halfsweep (identity patches, restricted)", False): 4.9824e8,
     ("k_pm_halfsweep (distorted patches)", False): 3.3994e8,
-    ("k_pm_halfsweep (identity patches, initial pass)", True): 9.8935e8,
-    ("k_pm_halfsweep (identity patches, restricted)", True): 3.2276e8,
-    ("k_pm_halfsweep (distorted patches)", True): 1.5298e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", True): 1.0070e9,
+    ("k_pm_halfsweep (identity patches, restricted)", True): 3.3779e8,
+    ("k_pm_halfsweep (distorted patches)", True): 1.5241e8,
 }
 
 

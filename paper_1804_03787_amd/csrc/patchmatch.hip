@@ -16,9 +16,11 @@
 // geometries (identity, integer translations) fetch one pixel per tap.  Column
 // partials are combined across the group in a fixed order, so every lane of the
 // group takes the same decisions.  Identity-patch candidates are evaluated in
-// batches whose gathers are in flight together; distorted-patch candidates one
-// at a time with an exact early rejection on partial sums (both schedules take
-// the decisions of a one-at-a-time loop).  Costs are accumulated in FP32.
+// batches whose first rows are gathered together, each then finished on its
+// own; distorted-patch candidates one at a time; both with exact early
+// rejections on partial sums (every schedule takes the decisions of a
+// one-at-a-time loop).  Costs are accumulated in FP32; FP16 records are
+// widened inside mixed-precision multiply-adds.
 //
 // PatchMatch (propagation + random search, as used by the paper for its NNF,
 // Sec. 3.1) runs as red-black Jacobi half-sweeps: a pixel reads only the other
