@@ -496,6 +496,17 @@ enum {
 msgpm_status msgpm_timing_enable(int on);
 msgpm_status msgpm_timing_read(double* ms, int64_t* launches);
 
+/* Self-check of the FP16-storage arithmetic on the current device (R30: the
+   FP16 form computes on the widened values).  The FP16 kernels widen halves
+   inside mixed-precision multiply-adds; this compares every such form with an
+   exact conversion followed by FP32 arithmetic, over all 65536 FP16 patterns
+   in both halves of a word and `rounds` partner operands per pattern (12
+   comparisons each).  Enqueued on `stream`; *d_mismatches, a device uint64,
+   receives the number of differing results (results that are both NaN are
+   not compared): 0 means the FP16 form's values are those of widening first.
+   rounds: 1..4096, else MSGPM_E_INVALID. */
+msgpm_status msgpm_check_fp16_arith(int32_t rounds, uint64_t* d_mismatches, void* stream);
+
 /* Counters in the workspace (uint64[16][64] at layout.counters: 16 counters,
    each kept as 64 partial sums to be added by the reader), per direction
    d = 0, 1, reset by msgpm_init_state:

@@ -246,6 +246,7 @@ hipError_t launch_unique(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_fill(const DevParams& P, const Ws& w, hipStream_t s);
 hipError_t launch_finalize(const DevParams& P, const Ws& w, float* flow0, float* flow1, uint8_t* occ0,
                            uint8_t* occ1, hipStream_t s);
+hipError_t launch_check_fp16_arith(int rounds, unsigned long long* out, hipStream_t s);
 
 // ---- batched launches -------------------------------------------------------
 enum BatchKind {

@@ -1087,6 +1087,16 @@ msgpm_status msgpm_tuning_get(msgpm_tuning* t) {
   return MSGPM_OK;
 }
 
+msgpm_status msgpm_check_fp16_arith(int32_t rounds, uint64_t* d_mismatches, void* stream) {
+  if (rounds < 1 || rounds > 4096 || !d_mismatches) return fail(MSGPM_E_INVALID, "rounds outside 1..4096 or NULL output");
+  if (reinterpret_cast<uintptr_t>(d_mismatches) & 7) return fail(MSGPM_E_INVALID, "output not 8-byte aligned");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MSGPM_E_DEVICE, "no device");
+  return check(launch_check_fp16_arith(rounds, reinterpret_cast<unsigned long long*>(d_mismatches),
+                                       static_cast<hipStream_t>(stream)),
+               "check_fp16_arith");
+}
+
 msgpm_status msgpm_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
   g_timer.on = on != 0;

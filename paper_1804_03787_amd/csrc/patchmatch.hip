@@ -1310,4 +1310,62 @@ int pm_batch_blocks(int kind, const DevParams& P, const int* a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Self-check of the mixed-precision helpers of the FP16 records against
+// widening first: thread i takes a word whose low half is FP16 pattern i (all
+// 65536 patterns over the grid) and whose high half is another pattern, and
+// compares every helper with the plain conversion-then-FP32 arithmetic for
+// `rounds` partner words and FP32 operands drawn by an integer hash.  Results
+// differ only where both are NaN (payloads are not compared).
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t check_mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ inline float widen(uint32_t u, bool hi) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(hi ? (u >> 16) : (u & 0xffffu)));
+}
+
+__device__ inline unsigned differs(float a, float b) {
+  return (__float_as_uint(a) != __float_as_uint(b) && !(a != a && b != b)) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_fp16_arith(int rounds, unsigned long long* out) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t ua = (i & 0xffffu) | ((check_mix32(i) & 0xffffu) << 16);
+  unsigned bad = 0;
+  for (int j = 0; j < rounds; ++j) {
+    const uint32_t ub = check_mix32(i * 131u + (uint32_t)j * 2654435761u);
+    const uint32_t r = check_mix32(ub ^ 0x9e3779b9u);
+    // FP32 operands over many magnitudes: a 24-bit mantissa scaled by 2^(e - 24)
+    const float f = ldexpf((float)(int)(r & 0xffffffu) - 8388608.f, (int)((r >> 24) & 31u) - 36);
+    const float w = ldexpf((float)(int)(check_mix32(r) & 0xffffffu) - 8388608.f, -23);
+    const float a0 = widen(ua, false), a1 = widen(ua, true), b0 = widen(ub, false), b1 = widen(ub, true);
+    bad += differs(sub_half<false>(f, ua), f - a0) + differs(sub_half<true>(f, ua), f - a1);
+    bad += differs(sub_halves<false, false>(ua, ub), a0 - b0) + differs(sub_halves<true, true>(ua, ub), a1 - b1);
+    bad += differs(sub_halves<true, false>(ua, ub), a1 - b0) + differs(sub_halves<false, true>(ua, ub), a0 - b1);
+    bad += differs(sub_half_f32<false>(ua, f), a0 - f) + differs(sub_half_f32<true>(ua, f), a1 - f);
+    bad += differs(fma_half<false>(ua, w, f), fmaf(a0, w, f)) + differs(fma_half<true>(ua, w, f), fmaf(a1, w, f));
+    bad += differs(mul_half<false>(ua, w), a0 * w + 0.f) + differs(mul_half<true>(ua, w), a1 * w + 0.f);
+  }
+  if (bad) atomicAdd(out, (unsigned long long)bad);
+}
+
+__global__ void k_check_clear(unsigned long long* out) {
+  if (threadIdx.x == 0) *out = 0ull;
+}
+
+hipError_t launch_check_fp16_arith(int rounds, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, s, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_check_fp16_arith, dim3(65536 / kBlock), dim3(kBlock), 0, s, rounds, out);
+  return hipGetLastError();
+}
+
 }  // namespace msgpm

@@ -121,6 +121,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_server_wait": [vp, u64, ctypes.c_int64],
             "msgpm_server_set_queue_limit": [vp, i],
             "msgpm_debug_fail_allocations": [i],
+            "msgpm_check_fp16_arith": [i, vp, vp],
         }.items():
             getattr(L, name).argtypes = args
             getattr(L, name).restype = ctypes.c_int
@@ -402,6 +403,17 @@ def _install_tuning(L):
             t.wg_per_cu[i] = int(entry["wg_per_cu"][k])
         if L.msgpm_tuning_set(ctypes.byref(t)) != 0:
             raise MsgpmError("msgpm_tuning_set", 1, f"{TUNING_PATH}: entry {key}")
+
+
+def check_fp16_arith(rounds: int = 256) -> tuple:
+    """msgpm_check_fp16_arith on the current device: (differing results, results
+    compared).  0 differing: the FP16 form's mixed-precision arithmetic gives
+    the values of widening first."""
+    import torch
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _call("msgpm_check_fp16_arith", int(rounds), _ptr(out), _stream())
+    torch.cuda.synchronize()
+    return int(out.item()), 65536 * int(rounds) * 12
 
 
 def debug_fail_allocations(n: int):

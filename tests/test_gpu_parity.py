@@ -385,6 +385,19 @@ def test_one_stream_flag_gives_the_same_result():
         assert np.array_equal(outs[0][2].view(np.uint8), other[2].view(np.uint8))
 
 
+def test_fp16_mixed_precision_arithmetic_equals_widening_first():
+    """msgpm_check_fp16_arith: every mixed-precision form the FP16 kernels use
+    (f - h, h - h', h - v, h * w + a, h * w + 0, with halves widened inside one
+    FMA) gives the bits of an exact conversion followed by FP32 arithmetic,
+    over all 65536 FP16 patterns in both halves of a word."""
+    msgpm = _need_gpu()
+    bad, total = msgpm.check_fp16_arith(256)
+    assert total == 65536 * 256 * 12
+    assert bad == 0, f"{bad} of {total} results differ"
+    with pytest.raises(msgpm.MsgpmError):
+        msgpm.check_fp16_arith(0)
+
+
 def test_invalid_arguments_raise():
     msgpm = _need_gpu()
     with pytest.raises(msgpm.MsgpmError):

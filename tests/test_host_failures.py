@@ -116,3 +116,15 @@ def test_no_device_is_a_device_error():
     v = ctypes.c_void_p(FAKE)
     st = _lib().msgpm_solve(ctypes.byref(p), v, v, None, None, v, v, v, v, v, None)
     assert st == msgpm.E_DEVICE, _err()
+
+
+def test_fp16_arith_check_argument_errors():
+    """msgpm_check_fp16_arith refuses bad arguments before any device work, and
+    reports E_DEVICE without a device."""
+    v = ctypes.c_void_p(FAKE)
+    assert _lib().msgpm_check_fp16_arith(0, v, None) == msgpm.E_INVALID
+    assert _lib().msgpm_check_fp16_arith(4097, v, None) == msgpm.E_INVALID
+    assert _lib().msgpm_check_fp16_arith(16, None, None) == msgpm.E_INVALID
+    assert _lib().msgpm_check_fp16_arith(16, ctypes.c_void_p(FAKE + 4), None) == msgpm.E_INVALID
+    if torch.cuda.device_count() == 0:
+        assert _lib().msgpm_check_fp16_arith(16, v, None) == msgpm.E_DEVICE
