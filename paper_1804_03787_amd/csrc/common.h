@@ -168,6 +168,21 @@ __device__ inline int xcd_remap(int bid, int nb) {
   return base + k;
 }
 
+// Full 128-bit product of two 64-bit words from four 32 x 32 -> 64-bit
+// multiply-adds (v_mad_u64_u32); no partial sum overflows, since
+// (2^32 - 1)^2 + 2 (2^32 - 1) < 2^64.  The compiler's own lowering of a 64-bit
+// product plus its high half recomputes the cross terms with separate 32-bit
+// multiplies (seven quarter-rate instructions instead of four).
+__device__ inline void mul64_wide(uint64_t a, uint64_t m, uint64_t& lo, uint64_t& hi) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+  const uint64_t p00 = (uint64_t)a0 * m0;
+  const uint64_t t = (uint64_t)a0 * m1 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a1 * m0 + (uint32_t)t;
+  lo = (u << 32) | (uint32_t)p00;
+  hi = (uint64_t)a1 * m1 + (t >> 32) + (u >> 32);
+}
+
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter c, key (k0, k1).
 __device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -178,8 +193,9 @@ __device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
       k0 += W0;
       k1 += W1;
     }
-    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    uint64_t lo0, hi0, lo1, hi1;
+    mul64_wide(c[0], M0, lo0, hi0);
+    mul64_wide(c[2], M1, lo1, hi1);
     const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;

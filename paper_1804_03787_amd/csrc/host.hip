@@ -155,9 +155,10 @@ msgpm_status prepare(const msgpm_params* p, DevParams* P, msgpm_layout* L) {
     return fail(MSGPM_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->fill_sweeps < 0 || p->fill_sweeps > 65536) return fail(MSGPM_E_INVALID, "fill_sweeps outside 0..65536");
   {
-    // kernels address one frame's features with 32-bit byte offsets
+    // kernels address one frame's features with 32-bit byte offsets, including
+    // the unclamped offsets of patch rows up to r rows beyond the last
     const uint64_t px_bytes = (p->flags & MSGPM_FLAG_FP16) ? (p->channels == 3 ? 8 : 12) : 4 * (uint64_t)p->channels;
-    if (((uint64_t)p->width * p->height + 1) * px_bytes > 0x7fffffffull)
+    if (((uint64_t)p->width * ((uint64_t)p->height + p->patch_radius) + 1) * px_bytes > 0x7fffffffull)
       return fail(MSGPM_E_UNSUPPORTED, "frame %dx%d: features exceed 2 GiB", p->width, p->height);
   }
 

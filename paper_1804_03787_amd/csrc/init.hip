@@ -232,7 +232,7 @@ __device__ __forceinline__ void init_pixels_body(const DevParams& P, const Ws& w
     tx = clampi(x + off_dx(v), 0, W - 1);
     ty = clampi(y + off_dy(v), 0, H - 1);
   } else {
-    uint64_t c[4] = {(uint64_t)p, 0, 0, rng_word3(1, dir, 0, 0)};
+    uint64_t c[4] = {(uint64_t)(uint32_t)p, 0, 0, rng_word3(1, dir, 0, 0)};
     philox4x64(c, P.seed, 0);
     tx = draw_below(c[0], (uint32_t)W);
     ty = draw_below(c[1], (uint32_t)H);

@@ -84,8 +84,9 @@ struct Px {
   }
   // The record of pixel idx as raw words (kWords of them), for tap_sq_raw.
   static constexpr int kWords = kBytes / 4;
-  static __device__ inline void raw1(Feat F, int idx, uint32_t* u) {
-    const int o = idx * kBytes;
+  static __device__ inline void raw1(Feat F, int idx, uint32_t* u) { raw1_at(F, idx * kBytes, u); }
+  // The same from the record's byte offset o.
+  static __device__ inline void raw1_at(Feat F, int o, uint32_t* u) {
     if constexpr (kWords == 5) {
       const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(F.r, o, 0, 0);
       u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
@@ -621,6 +622,29 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const uint8_t* __restrict
 //  * distorted patches (long chain, register-heavy): one candidate at a time
 //    with the exact early rejection of group_cost.
 
+// Byte offsets of the records of an identity-patch target (tx, ty) in a lane's
+// column dx: record (clamp(tx + dx), clamp(ty + t - R)) of row t.  The row
+// clamp commutes with the multiplication by the row pitch (positive), and a
+// clamp commutes with adding the column's offset, so that a row costs one add
+// of a wave-uniform term and one three-way median on a per-target base and
+// bounds, instead of a clamp, a multiply-add and a multiply.
+template <int R, int KB>
+struct IdentAddr {
+  int base, lo, hi, pitch;
+  IdentAddr() = default;
+  __device__ inline IdentAddr(int tx, int ty, int dx, int W, int H) {
+    pitch = W * KB;
+    lo = clampi(tx + dx, 0, W - 1) * KB;
+    hi = lo + (H - 1) * pitch;
+    base = lo + (ty - R) * pitch;
+  }
+  __device__ inline int at(int t) const {
+    int o;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(o) : "v"(base + t * pitch), "v"(lo), "v"(hi));
+    return o;
+  }
+};
+
 // Tap rows per load chunk of identity-patch batches: one (measured on MI355X, two
 // or three rows per chunk take the kernel to 256 VGPRs and lose more than the
 // longer chunks gain).
@@ -638,6 +662,9 @@ constexpr int kIdentStep = 3;
 template <int R, int C, bool FP16, int NB, int T0, int T>
 __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                   const int* ty, float gw) {
+  IdentAddr<R, Px<C, FP16>::kBytes> A[NB] = {};
+#pragma unroll
+  for (int b = 0; b < NB; ++b) A[b] = IdentAddr<R, Px<C, FP16>::kBytes>(tx[b], ty[b], L.dx, W, H);
 #pragma unroll
   for (int t0 = T0; t0 < T; t0 += kIdentRows) {
     constexpr int TC = kIdentRows;
@@ -646,11 +673,7 @@ __device__ inline void ident_rows(float* acc, const LaneCol<R, C, true>& L, Feat
     for (int u = 0; u < TC; ++u)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        if (t0 + u < T) {
-          const int bx = clampi(tx[b] + L.dx, 0, W - 1);
-          const int by = clampi(ty[b] + t0 + u - R, 0, H - 1);
-          Px<C, FP16>::raw1(F2, by * W + bx, v[u][b]);
-        }
+        if (t0 + u < T) Px<C, FP16>::raw1_at(F2, A[b].at(t0 + u), v[u][b]);
       }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -669,12 +692,9 @@ __device__ inline float ident_rows1(float acc, const LaneCol<R, C, true>& L, Fea
                                     float gw) {
   constexpr int N = T - T0;
   uint32_t v[N][Px<C, FP16>::kWords];
-  const int bx = clampi(tx + L.dx, 0, W - 1);
+  const IdentAddr<R, Px<C, FP16>::kBytes> A(tx, ty, L.dx, W, H);
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
-    const int by = clampi(ty + T0 + n - R, 0, H - 1);
-    Px<C, FP16>::raw1(F2, by * W + bx, v[n]);
-  }
+  for (int n = 0; n < N; ++n) Px<C, FP16>::raw1_at(F2, A.at(T0 + n), v[n]);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int n = 0; n < N; ++n) acc += tap_sq_raw<C, FP16>(L.f1[T0 + n], v[n], gw);
@@ -1076,7 +1096,7 @@ __device__ __forceinline__ void pm_halfsweep_body(const DevParams& P, const Ws& 
       rox[h] = roy[h] = 0;
       if (k < P.nk) {
         const int Rk = P.R0 >> k;
-        uint64_t c[4] = {(uint64_t)p, (uint64_t)k, (uint64_t)iter, w3};
+        uint64_t c[4] = {(uint64_t)(uint32_t)p, (uint64_t)k, (uint64_t)iter, w3};
         philox4x64(c, P.seed, 0);
         rox[h] = draw_below(c[0], (uint32_t)(2 * Rk + 1)) - Rk;
         roy[h] = draw_below(c[1], (uint32_t)(2 * Rk + 1)) - Rk;

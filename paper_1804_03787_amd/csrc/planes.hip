@@ -315,7 +315,7 @@ __device__ inline bool inlier8(const double* H, double x, double y, double qx, d
 // permutation of the n points, degeneracy test, normalised DLT.
 __device__ inline bool make_hypothesis(const DevParams& P, int b, int h, int n, uint64_t w3, const uint32_t* src,
                                        const uint32_t* dst, double* Hout) {
-  uint64_t c[4] = {(uint64_t)b, (uint64_t)h, 0, w3};
+  uint64_t c[4] = {(uint64_t)(uint32_t)b, (uint64_t)h, 0, w3};
   philox4x64(c, P.seed, 0);
   int key[8], val[8], nm = 0, sel[4];
 #pragma unroll
