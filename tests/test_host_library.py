@@ -85,6 +85,22 @@ def test_layout_query_rejects_unknown_flags():
     assert b"flags" in msgpm.lib().msgpm_last_error()
 
 
+@pytest.mark.parametrize("fp16,r,h_max", [(False, 4, 3272), (True, 1, 5460)])
+def test_feature_offsets_limit_includes_patch_rows_past_the_frame(fp16, r, h_max):
+    """Feature byte offsets are 32-bit and the identity-patch rows are offset
+    before their clamp, up to r rows past the last: a 32767-wide frame is
+    accepted up to the largest height with (W (H + r) + 1) * record bytes
+    < 2^31 and refused (unsupported) one row above it."""
+    W = 32767
+    rec = 12 if fp16 else 20
+    assert (W * (h_max + r) + 1) * rec <= 2**31 - 1 < (W * (h_max + 1 + r) + 1) * rec
+    p = msgpm.make_params(W, h_max, fp16=fp16, r=r)
+    assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) == 0
+    p = msgpm.make_params(W, h_max + 1, fp16=fp16, r=r)
+    assert msgpm.lib().msgpm_layout_query(ctypes.byref(p), ctypes.byref(msgpm.Layout())) == msgpm.E_UNSUPPORTED
+    assert b"exceed 2 GiB" in msgpm.lib().msgpm_last_error()
+
+
 REGIONS = ["feat", "nnf", "cost", "win", "loss", "hlabel", "twin", "tloss", "planes", "counters", "histeq", "active"]
 
 
