@@ -363,7 +363,7 @@ __device__ inline float tap_sq_packed(const float* f1, const float* v, float gw)
 // LDS by 0.1 ms per pair with FP32 records and 1.6 ms with FP16 records).  Groups never
 // straddle inactive lanes: a group is active or inactive as a whole.
 template <int G>
-__device__ inline float group_sum(float v, int base) {
+__device__ inline float group_chain(float v) {
   float s = v;
 #pragma unroll
   for (int k = 1; k < G; ++k) {
@@ -371,6 +371,12 @@ __device__ inline float group_sum(float v, int base) {
         __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s), 0x138, 0xf, 0xf, false));
     s = sh + v;
   }
+  return s;
+}
+
+template <int G>
+__device__ inline float group_sum(float v, int base) {
+  const float s = group_chain<G>(v);
   constexpr int NG = kWave / G;
   if constexpr (NG <= 9) {
     // few groups: read each group's last lane and select, no LDS round trip
@@ -384,6 +390,17 @@ __device__ inline float group_sum(float v, int base) {
   } else {
     return __shfl(s, base + G - 1);
   }
+}
+
+// A decision taken at the group's last lane (where group_chain leaves the
+// group's sum), handed to every lane of the group through one wave ballot:
+// what a comparison of the broadcast sum would give on every lane, without
+// the broadcast.  Values compared with such a sum (the running best cost of
+// the identity-patch search) then need to be right only at the last lane.
+template <int G>
+__device__ inline bool group_flag(bool at_last, int base) {
+  const unsigned long long m = __ballot(at_last);
+  return (m >> (base + G - 1)) & 1ull;
 }
 
 __device__ inline const double* plane_H(const Ws& w, int label) {
@@ -715,7 +732,7 @@ __device__ inline bool ident_finish(float& a, float acc, const LaneCol<R, C, tru
     rows += T;
     return true;
   } else {
-    if (!(group_sum<T>(acc, base) < bound)) {
+    if (!group_flag<T>(group_chain<T>(acc) < bound, base)) {
       rows += T1;
       return false;
     }
@@ -735,7 +752,10 @@ __device__ inline bool ident_finish(float& a, float acc, const LaneCol<R, C, tru
 // take part in it).  A finished target is summed in the same order as a lone
 // evaluation.  FP16 records (one load per tap) gather all rows of the batch
 // together and skip the checks: measured on MI355X, finishing each target on
-// its own makes the FP16 pipeline 3 % slower.
+// its own makes the FP16 pipeline 3 % slower.  Every comparison is taken at
+// the group's last lane, where the lane-order sum forms, and handed to the
+// group by a ballot (group_flag), so the running best cost bc is exact at
+// that lane only.
 template <int R, int C, bool FP16, int NB>
 __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                    const int* ty, const bool* ok, float gw, int base, int& btx, int& bty, float& bc,
@@ -753,14 +773,14 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
     ident_rows<R, C, FP16, NB, TE, T>(acc, L, F2, W, H, tx, ty, gw);
     float c[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) c[b] = group_sum<T>(acc[b], base);
+    for (int b = 0; b < NB; ++b) c[b] = group_chain<T>(acc[b]);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (!ok[b]) continue;
       ++evals;
       rows += T;
       if (tx[b] == btx && ty[b] == bty) continue;
-      if (c[b] < bc) {
+      if (group_flag<T>(c[b] < bc, base)) {
         bc = c[b];
         btx = tx[b];
         bty = ty[b];
@@ -770,19 +790,19 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
     ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
     float pre[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) pre[b] = group_sum<T>(acc[b], base);
+    for (int b = 0; b < NB; ++b) pre[b] = group_chain<T>(acc[b]);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (!ok[b]) continue;
       ++evals;
-      if ((tx[b] == btx && ty[b] == bty) || !(pre[b] < bc)) {
+      if ((tx[b] == btx && ty[b] == bty) || !group_flag<T>(pre[b] < bc, base)) {
         rows += TE;
         continue;
       }
       float a;
       if (!ident_finish<R, C, FP16, TE>(a, acc[b], L, F2, W, H, tx[b], ty[b], gw, base, bc, rows)) continue;
-      const float c = group_sum<T>(a, base);
-      if (c < bc) {
+      const float c = group_chain<T>(a);
+      if (group_flag<T>(c < bc, base)) {
         bc = c;
         btx = tx[b];
         bty = ty[b];
@@ -873,7 +893,8 @@ __device__ inline void pm_candidates_ident(const LaneCol<R, C, true>& L, const D
     random_batch<R, C, FP16, NB>(L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals, rows);
   random_rest<R, C, FP16, NB - 1>(P.nk - k0, L, P, F2, x, y, cdx, cdy, k0, base, rox, roy, btx, bty, bc, evals,
                                   rows);
-  if (base == (int)(threadIdx.x & (kWave - 1))) {
+  // the running best cost is exact at the group's last lane (group_flag)
+  if (base + 2 * R == (int)(threadIdx.x & (kWave - 1))) {
     w.nnf[dir][p] = pack_off(btx - x, bty - y);
     w.cost[dir][p] = bc;
   }
