@@ -61,12 +61,12 @@ PEAK_LDS_GBS = 78643.2
 # kernels as they are now.
 TRAFFIC = {
     # profiles/k_pm_halfsweep_1024x436_traffic.md
-    ("k_pm_halfsweep (identity patches, initial pass)", False): 1.9673e9,
-    ("k_pm_halfsweep (identity patches, restricted)", False): 4.9782e8,
-    ("k_pm_halfsweep (distorted patches)", False): 3.3838e8,
-    ("k_pm_halfsweep (identity patches, initial pass)", True): 1.0092e9,
-    ("k_pm_halfsweep (identity patches, restricted)", True): 3.3632e8,
-    ("k_pm_halfsweep (distorted patches)", True): 1.5191e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", False): 1.9691e9,
+    ("k_pm_halfsweep (identity patches, restricted)", False): 4.9611e8,
+    ("k_pm_halfsweep (distorted patches)", False): 3.3862e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", True): 1.0057e9,
+    ("k_pm_halfsweep (identity patches, restricted)", True): 3.3791e8,
+    ("k_pm_halfsweep (distorted patches)", True): 1.5169e8,
 }
 
 
