@@ -355,13 +355,10 @@ __device__ inline float tap_sq_packed(const float* f1, const float* v, float gw)
   return row;
 }
 
-// Sum of the group's column partials in lane order, identical on every lane
-// of the group.  Eight adds with the wave shifted right by one lane leave at
-// lane l the sum ((v[l-G+1] + v[l-G+2]) + ...) + v[l]; at the group's last lane
-// that is its G partials in lane order, which is then broadcast (by lane reads
-// for up to nine groups: measured on MI355X, faster than a permute through
-// LDS by 0.1 ms per pair with FP32 records and 1.6 ms with FP16 records).  Groups never
-// straddle inactive lanes: a group is active or inactive as a whole.
+// G - 1 adds with the wave shifted right by one lane leave at lane l the sum
+// ((v[l-G+1] + v[l-G+2]) + ...) + v[l]; at the group's last lane that is the
+// group's G column partials in lane order.  Groups never straddle inactive
+// lanes: a group is active or inactive as a whole.
 template <int G>
 __device__ inline float group_chain(float v) {
   float s = v;
@@ -374,6 +371,10 @@ __device__ inline float group_chain(float v) {
   return s;
 }
 
+// Sum of the group's column partials in lane order, identical on every lane
+// of the group: group_chain's value at the last lane, broadcast (by lane reads
+// for up to nine groups: measured on MI355X, faster than a permute through
+// LDS by 0.1 ms per pair with FP32 records and 1.6 ms with FP16 records).
 template <int G>
 __device__ inline float group_sum(float v, int base) {
   const float s = group_chain<G>(v);
