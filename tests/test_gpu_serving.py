@@ -116,6 +116,8 @@ def test_serving_cancel_queued_and_in_flight():
                 done[t] = True
         if len(done) == 2:
             break
+    # a step after both polls (the work may finish between a step and the polls)
+    pend = srv.step()
     assert len(done) == 2 and pend == 0
     g, flows, occs = srv.result(ts[0])
     _same(alone[0], _outputs(g, flows, occs))
