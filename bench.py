@@ -306,6 +306,7 @@ def run_serving(args) -> int:
     def serve(reqs, max_active=64, budget=200 << 30):
         """Returns (latencies in s, makespan in s, Mpix)."""
         srv = msgpm.Server(budget, max_active)
+        srv.set_cohorts(args.cohorts)
         lat, out, cls = [], {}, []
         mpix = sum(SERVE_SIZES[c][0][0] * SERVE_SIZES[c][0][1] for _, c, _ in reqs) / 1e6
         torch.cuda.synchronize()
@@ -427,7 +428,7 @@ def run_serving(args) -> int:
         "config": {"workload": "Poisson arrivals; sizes 50% 1024x436, 30% 640x360, 20% 2048x872 (windows "
                                "128/64/32/16); patch 9x9, C=5, 8 PM iterations, 256 RANSAC hypotheses; FP16 "
                                "storage; continuous batching",
-                   "duration_s": args.duration},
+                   "duration_s": args.duration, "cohorts": args.cohorts},
         "capacity_mpix_s": round(capacity, 3),
         "batched_same_requests_mpix_s": round(batched_same, 3),
         "runs": runs,
@@ -466,6 +467,7 @@ def main() -> int:
     ap.add_argument("--serving", action="store_true", help="serving workload: Poisson arrivals, continuous batching")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
+    ap.add_argument("--cohorts", type=int, default=4, help="serving: cohorts in flight at most (1..4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the pipeline runs on one GPU; --gpus {args.gpus} is not supported "

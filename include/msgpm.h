@@ -416,8 +416,9 @@ msgpm_status msgpm_tuning_get(msgpm_tuning* t);
  * uploaded and the batched pipeline of msgpm_solve_batch_graph runs as one
  * graph launch (one graph per schedule and region, captured once), on one of
  * the server's own streams, ordered after the work already on `stream`.  Up to
- * four cohorts run on the device side by side, so pairs that arrive while
- * others are on the GPU start at once and share it with them.  A pair's
+ * four cohorts (msgpm_server_set_cohorts) run on the device side by side, so
+ * pairs that arrive while others are on the GPU start at once and share it
+ * with them.  A pair's
  * results (as msgpm_solve, and identical to them) are complete once
  * msgpm_server_poll reports it done or msgpm_server_wait returns; its ticket
  * is then retired.  All pairs of a server share patch_radius, channels and the
@@ -442,6 +443,15 @@ msgpm_status msgpm_server_submit(msgpm_server* server, const msgpm_params* p, co
                                  uint64_t* ticket);
 /* Largest number of pairs waiting for admission (0 = no limit, the default). */
 msgpm_status msgpm_server_set_queue_limit(msgpm_server* server, int max_queued);
+/* Largest number of cohorts in flight, 1..MSGPM_SERVER_MAX_COHORTS (the
+   default); MSGPM_E_INVALID outside that range.  It trades the median latency
+   for the tail: with one cohort at a time, pairs that arrive in a burst queue
+   for the GPU instead of sharing it, and the p99 latency is lowest; with four,
+   the median is.  The throughput at capacity does not depend on it (a cohort
+   of several pairs fills the GPU).  Takes effect at the next step; cohorts
+   already in flight run to their end. */
+#define MSGPM_SERVER_MAX_COHORTS 4
+msgpm_status msgpm_server_set_cohorts(msgpm_server* server, int cohorts);
 /* *pending: pairs queued or not yet done after this step. */
 msgpm_status msgpm_server_step(msgpm_server* server, void* d_scratch, void* stream, int* pending);
 msgpm_status msgpm_server_poll(msgpm_server* server, uint64_t ticket, int* done);

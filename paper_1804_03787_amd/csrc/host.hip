@@ -1136,11 +1136,11 @@ msgpm_status msgpm_timing_read(double* ms, int64_t* launches) {
 // Each msgpm_server_step admits the queued pairs that fit (first come, first
 // served, one schedule per cohort) as one cohort and enqueues its whole
 // pipeline as one batched graph launch on one of the server's streams; up to
-// kCohorts cohorts run on the device side by side, each with its own region
+// max_cohorts (at most kCohorts) cohorts run on the device side by side, each with its own region
 // of the caller's scratch for its table.
 namespace {
 
-constexpr int kCohorts = 4;          // cohorts in flight (and server streams)
+constexpr int kCohorts = MSGPM_SERVER_MAX_COHORTS;  // cohorts in flight at most (and server streams)
 constexpr int kMaxLaunches = 4096;   // launches of one pipeline a region holds
 constexpr int kMaxLists = 48;        // distinct item lists of one pipeline
 
@@ -1174,6 +1174,7 @@ struct msgpm_server {
   uint64_t budget = 0;
   int max_active = 0;
   int max_queued = 0;  // 0 = no limit
+  int max_cohorts = kCohorts;  // cohorts in flight at most
   uint64_t next_ticket = 1;
   uint64_t in_use = 0;
   int in_flight = 0;
@@ -1329,12 +1330,16 @@ msgpm_status msgpm_server_step(msgpm_server* sv, void* d_scratch, void* stream, 
   server_retire(sv);
   if (pending) *pending = (int)sv->queue.size() + sv->in_flight;
   if (sv->queue.empty()) return MSGPM_OK;
-  int ci = -1;
-  for (int k = 0; k < kCohorts && ci < 0; ++k) {
+  int ci = -1, busy = 0;
+  for (int k = 0; k < kCohorts; ++k) {
     const int c = (sv->next + k) % kCohorts;
-    if (!sv->cohorts[c].busy) ci = c;
+    if (sv->cohorts[c].busy)
+      ++busy;
+    else if (ci < 0)
+      ci = c;
   }
-  if (ci < 0) return MSGPM_OK;  // every region in use: admitted at a later step
+  // every region in use, or the cohort limit reached: admitted at a later step
+  if (ci < 0 || busy >= sv->max_cohorts) return MSGPM_OK;
   // the cohort: queued pairs with the head's schedule, first come first served,
   // while the budget and the in-flight limit allow
   std::vector<Slot*> take;
@@ -1414,6 +1419,14 @@ msgpm_status msgpm_server_set_queue_limit(msgpm_server* sv, int max_queued) {
   if (!sv || max_queued < 0) return fail(MSGPM_E_INVALID, "server is NULL or limit negative");
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->max_queued = max_queued;
+  return MSGPM_OK;
+}
+
+msgpm_status msgpm_server_set_cohorts(msgpm_server* sv, int cohorts) {
+  if (!sv || cohorts < 1 || cohorts > kCohorts)
+    return fail(MSGPM_E_INVALID, "server is NULL or cohorts outside 1..%d", kCohorts);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->max_cohorts = cohorts;
   return MSGPM_OK;
 }
 

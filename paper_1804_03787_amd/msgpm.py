@@ -22,6 +22,7 @@ FLAG_CUE_UNIQUE = 4   # occlusion cue 2: one assigned pixel per target
 FLAG_HISTEQ = 8       # equalise the frames' HSV value channel before the features
 FLAG_MERGE_STRICT = 16  # strict level priority: a later level assigns only unassigned pixels
 FLAG_ONE_STREAM = 32  # restricted half-sweeps' two launches in sequence on the caller's stream
+SERVER_MAX_COHORTS = 4  # cohorts a server runs side by side at most (msgpm_server_set_cohorts)
 PM_FRESH = 2          # pm_halfsweep: compute each swept pixel's current cost first (folds the cost refresh in)
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_DEVICE", 4: "E_UNSUPPORTED", 5: "E_BUSY", 6: "E_CANCELLED",
@@ -120,6 +121,7 @@ def lib() -> ctypes.CDLL:
             "msgpm_server_cancel": [vp, u64, ctypes.POINTER(i)],
             "msgpm_server_wait": [vp, u64, ctypes.c_int64],
             "msgpm_server_set_queue_limit": [vp, i],
+            "msgpm_server_set_cohorts": [vp, i],
             "msgpm_debug_fail_allocations": [i],
             "msgpm_check_fp16_arith": [i, vp, vp],
         }.items():
@@ -520,6 +522,10 @@ class Server:
 
     def set_queue_limit(self, max_queued: int):
         _call("msgpm_server_set_queue_limit", self.h, int(max_queued))
+
+    def set_cohorts(self, cohorts: int):
+        """Largest number of cohorts in flight (msgpm_server_set_cohorts)."""
+        _call("msgpm_server_set_cohorts", self.h, int(cohorts))
 
     def cancel(self, ticket: int) -> bool:
         """Cancels a pair; True if it was still queued and is gone already (an

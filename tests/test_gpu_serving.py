@@ -28,7 +28,9 @@ def _scenes():
     ]
 
 
-def test_serving_mix_matches_single_solves():
+@pytest.mark.parametrize("cohorts", [4, 1])
+def test_serving_mix_matches_single_solves(cohorts):
+    """Also with one cohort in flight at a time (msgpm_server_set_cohorts)."""
     msgpm = _need_gpu()
     scenes = _scenes()
     alone = []
@@ -37,6 +39,7 @@ def test_serving_mix_matches_single_solves():
         g = msgpm.Pair(W, H, **p)
         alone.append(_outputs(g, *g.solve(pr.frame1, pr.frame2)))
     srv = msgpm.Server(hbm_budget=1 << 34, max_active=3)
+    srv.set_cohorts(cohorts)
     arrivals = {0: [0, 1], 5: [2, 3], 12: [4], 30: [5]}   # round -> scenes submitted before it
     tickets, done = {}, {}
     rnd = 0

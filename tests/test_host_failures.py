@@ -61,6 +61,10 @@ def test_full_queue_is_a_transient_refusal_and_waits_time_out():
     h = _server(1 << 40)
     assert _lib().msgpm_server_set_queue_limit(h, 2) == 0
     assert _lib().msgpm_server_set_queue_limit(h, -1) == msgpm.E_INVALID
+    for n, want in ((0, msgpm.E_INVALID), (msgpm.SERVER_MAX_COHORTS + 1, msgpm.E_INVALID), (1, 0),
+                    (msgpm.SERVER_MAX_COHORTS, 0)):
+        assert _lib().msgpm_server_set_cohorts(h, n) == want, n
+    assert _lib().msgpm_server_set_cohorts(None, 1) == msgpm.E_INVALID
     st1, t1 = _submit(h, p)
     st2, t2 = _submit(h, p)
     assert st1 == 0 and st2 == 0 and t1 != t2

@@ -33,6 +33,7 @@ def test_binding_constants_match_the_header():
     assert len(codes) == 8
     for name, v in codes.items():
         assert msgpm.STATUS[int(v)] == name, name
+    assert int(re.search(r"#define MSGPM_SERVER_MAX_COHORTS (\d+)", text).group(1)) == msgpm.SERVER_MAX_COHORTS
 
 
 def test_one_stream_flag_is_accepted():
