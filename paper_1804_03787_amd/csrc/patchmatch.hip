@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void kb_eval_cost(const uint8_t* __restrict
 //  * identity patches (short per-candidate chain): candidates in batches of
 //    NB; the first third of the rows of the batch is gathered together, then
 //    each candidate still in the running is finished on its own, with exact
-//    early rejections per lane group (FP32 records);
+//    early rejections per lane group;
 //  * distorted patches (long chain, register-heavy): one candidate at a time
 //    with the exact early rejection of group_cost.
 
@@ -667,9 +667,9 @@ struct IdentAddr {
 // or three rows per chunk take the kernel to 256 VGPRs and lose more than the
 // longer chunks gain).
 constexpr int kIdentRows = 1;
-// Rows per step when one identity-patch candidate is finished (FP32 records),
-// with an early-rejection check before each step.  Measured on MI355X at
-// 1024x436 (whole pipeline, r = 4): checks at rows 3 and 6 take 33.1 ms per
+// Rows per step when one identity-patch candidate is finished, with an
+// early-rejection check before each step.  Measured on MI355X at 1024x436
+// (whole pipeline, r = 4, FP32 records): checks at rows 3 and 6 take 33.1 ms per
 // pair, a check at row 3 only 33.9 ms, checks at rows 3, 5 and 7 33.8 ms,
 // one at every row 38.2 ms; the batch-wide check this replaced took 37.3 ms.
 constexpr int kIdentStep = 3;
@@ -751,12 +751,13 @@ __device__ inline bool ident_finish(float& a, float acc, const LaneCol<R, C, tru
 // group: the lanes of a dropped target sit out its remaining gathers, which
 // is where the time goes (the cost of a gather scales with the lanes that
 // take part in it).  A finished target is summed in the same order as a lone
-// evaluation.  FP16 records (one load per tap) gather all rows of the batch
-// together and skip the checks: measured on MI355X, finishing each target on
-// its own makes the FP16 pipeline 3 % slower.  Every comparison is taken at
-// the group's last lane, where the lane-order sum forms, and handed to the
-// group by a ballot (group_flag), so the running best cost bc is exact at
-// that lane only.
+// evaluation.  Every comparison is taken at the group's last lane, where the
+// lane-order sum forms, and handed to the group by a ballot (group_flag), so
+// the running best cost bc is exact at that lane only.  Both record formats
+// use this form; with FP16 records (one load per tap) it was 3 % slower than
+// gathering all rows of the batch and skipping the checks while the kernel's
+// VALU work bound it, and after the per-target row offsets and the ballot
+// decisions it is 7 % faster (measured on MI355X, 1024x436).
 template <int R, int C, bool FP16, int NB>
 __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W, int H, const int* tx,
                                    const int* ty, const bool* ok, float gw, int base, int& btx, int& bty, float& bc,
@@ -769,45 +770,25 @@ __device__ inline void ident_batch(const LaneCol<R, C, true>& L, Feat F2, int W,
   float acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.f;
-  if constexpr (FP16) {
-    ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
-    ident_rows<R, C, FP16, NB, TE, T>(acc, L, F2, W, H, tx, ty, gw);
-    float c[NB];
+  ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
+  float pre[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) c[b] = group_chain<T>(acc[b]);
+  for (int b = 0; b < NB; ++b) pre[b] = group_chain<T>(acc[b]);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (!ok[b]) continue;
-      ++evals;
-      rows += T;
-      if (tx[b] == btx && ty[b] == bty) continue;
-      if (group_flag<T>(c[b] < bc, base)) {
-        bc = c[b];
-        btx = tx[b];
-        bty = ty[b];
-      }
+  for (int b = 0; b < NB; ++b) {
+    if (!ok[b]) continue;
+    ++evals;
+    if ((tx[b] == btx && ty[b] == bty) || !group_flag<T>(pre[b] < bc, base)) {
+      rows += TE;
+      continue;
     }
-  } else {
-    ident_rows<R, C, FP16, NB, 0, TE>(acc, L, F2, W, H, tx, ty, gw);
-    float pre[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) pre[b] = group_chain<T>(acc[b]);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (!ok[b]) continue;
-      ++evals;
-      if ((tx[b] == btx && ty[b] == bty) || !group_flag<T>(pre[b] < bc, base)) {
-        rows += TE;
-        continue;
-      }
-      float a;
-      if (!ident_finish<R, C, FP16, TE>(a, acc[b], L, F2, W, H, tx[b], ty[b], gw, base, bc, rows)) continue;
-      const float c = group_chain<T>(a);
-      if (group_flag<T>(c < bc, base)) {
-        bc = c;
-        btx = tx[b];
-        bty = ty[b];
-      }
+    float a;
+    if (!ident_finish<R, C, FP16, TE>(a, acc[b], L, F2, W, H, tx[b], ty[b], gw, base, bc, rows)) continue;
+    const float c = group_chain<T>(a);
+    if (group_flag<T>(c < bc, base)) {
+      bc = c;
+      btx = tx[b];
+      bty = ty[b];
     }
   }
 }
