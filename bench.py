@@ -64,9 +64,9 @@ TRAFFIC = {
     ("k_pm_halfsweep (identity patches, initial pass)", False): 1.9691e9,
     ("k_pm_halfsweep (identity patches, restricted)", False): 4.9611e8,
     ("k_pm_halfsweep (distorted patches)", False): 3.3862e8,
-    ("k_pm_halfsweep (identity patches, initial pass)", True): 1.0057e9,
-    ("k_pm_halfsweep (identity patches, restricted)", True): 3.3791e8,
-    ("k_pm_halfsweep (distorted patches)", True): 1.5169e8,
+    ("k_pm_halfsweep (identity patches, initial pass)", True): 5.9985e8,
+    ("k_pm_halfsweep (identity patches, restricted)", True): 1.9960e8,
+    ("k_pm_halfsweep (distorted patches)", True): 1.5155e8,
 }
 
 
